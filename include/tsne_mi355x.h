@@ -1,0 +1,212 @@
+/*
+ * tsne_mi355x.h -- C ABI of the MI355X (gfx950) exact t-SNE hot path.
+ *
+ * The single-cell workflow profiled in the paper spends one of its most
+ * GPU-intensive stages in t-SNE of PCA scores (abstract; Table 1, row 7,
+ * "Umap + t-sne").  The paper names the stage but defines none of its steps,
+ * so each entry point below computes the standard published definition it
+ * cites:
+ *   [vdMH08] van der Maaten & Hinton, JMLR 9 (2008), "Visualizing Data
+ *            using t-SNE": eq. 1 (conditional P), eq. 3 (perplexity),
+ *            Sec. 3.1 (symmetric P), eq. 4 (Student-t Q), eq. 5 (gradient),
+ *            Sec. 3.4 / Algorithm 1 (momentum, early exaggeration).
+ *   [vdM14]  van der Maaten, JMLR 15 (2014), "Accelerating t-SNE using
+ *            Tree-Based Algorithms", Sec. 4.1 (sparse P on the exact
+ *            k = 3*perplexity nearest-neighbour graph).
+ *   [Jac88]  Jacobs, Neural Networks 1 (1988): per-parameter gains.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Every array argument is a DEVICE pointer on the current HIP
+ *           device, owned by the caller, 16-byte aligned, in the layout
+ *           stated.  The library never allocates or frees memory and keeps
+ *           no state between calls.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ *           stream).  Work is enqueued and the call returns without a host
+ *           synchronisation.  Scalars the host may want (nnz, Z, KL, counts)
+ *           are written to caller-provided device scalars.
+ * Workspace. Entry points that need scratch take (void* workspace,
+ *           size_t* workspace_bytes).  With workspace == NULL the call only
+ *           stores the required byte count in *workspace_bytes and returns
+ *           TSNE_OK without touching the device.  Otherwise *workspace_bytes
+ *           must be at least that size (else TSNE_ERR_WORKSPACE); the
+ *           workspace must be device memory aligned to 256 bytes; its
+ *           contents on entry are ignored.
+ * Errors.   Arguments are validated before any HIP call; invalid ones
+ *           return TSNE_ERR_INVALID_ARG or TSNE_ERR_UNSUPPORTED and enqueue
+ *           nothing.  A failed launch returns TSNE_ERR_HIP and its
+ *           hipError_t is kept per thread (tsne_last_hip_error).
+ *           Asynchronous device faults surface at the caller's next
+ *           synchronisation.  No C++ exception crosses the ABI.
+ * Threads.  Re-entrant; concurrent calls on different streams with
+ *           disjoint buffers are safe.
+ * Results.  Deterministic for fixed inputs and device: no floating-point
+ *           atomics, every reduction in a fixed order.
+ */
+#ifndef TSNE_MI355X_H
+#define TSNE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSNE_ABI_VERSION 1
+
+#define TSNE_OK 0
+#define TSNE_ERR_INVALID_ARG 1
+#define TSNE_ERR_UNSUPPORTED 2
+#define TSNE_ERR_WORKSPACE 3
+#define TSNE_ERR_HIP 4
+
+/* precision argument of tsne_knn */
+#define TSNE_KNN_FP32 0 /* exact: FP32 direct differences on the VALU */
+#define TSNE_KNN_BF16 1 /* BF16 MFMA candidates, FP32 exact re-rank */
+
+/* dtype argument of the differentiation form */
+#define TSNE_F32 0
+#define TSNE_F64 1
+
+/* Largest supported neighbour count k and BF16 candidate count. */
+#define TSNE_MAX_K 256
+/* Largest supported input dimension D. */
+#define TSNE_MAX_D 256
+/* BF16 path: D plus 6 norm slots must fit the 64-wide MFMA K extent. */
+#define TSNE_MAX_D_BF16 58
+
+int tsne_abi_version(void);
+const char* tsne_status_string(int status);
+/* hipError_t (as int) of the last TSNE_ERR_HIP returned on this thread. */
+int tsne_last_hip_error(void);
+
+/*
+ * tsne_knn -- exact k nearest neighbours [vdM14 Sec. 4.1].
+ * For every row i of X: the k indices j != i with the smallest squared
+ * Euclidean distance d_ij = sum_c (x_ic - x_jc)^2 (the distance inside the
+ * Gaussian kernel of [vdMH08] eq. 1), ordered ascending by the key
+ * (d_ij, j); self is excluded by index, ties go to the smaller index.
+ *
+ *   X        [n][d] float, row-major, read-only.
+ *   n, d     2 <= n < 2^31; 1 <= d <= TSNE_MAX_D (TSNE_MAX_D_BF16 for BF16).
+ *   k        1 <= k < n, k <= TSNE_MAX_K.
+ *   precision TSNE_KNN_FP32: distances are FP32 direct differences summed
+ *            in dimension order; the key order is exact in that arithmetic.
+ *            TSNE_KNN_BF16: X is rounded to bfloat16 (round-to-nearest-even);
+ *            MFMA tiles with FP32 accumulation give the distances between
+ *            rounded points; the n_cand smallest of those per row are then
+ *            re-ranked by FP32 direct differences on the unrounded X and the
+ *            best k kept.  An approximation: a true neighbour is lost only if
+ *            bf16 rounding pushes it past rank n_cand.
+ *   n_cand   BF16 only: k <= n_cand < n, n_cand <= TSNE_MAX_K (ignored for FP32).
+ *   nbr_idx  [n][k] int32 out; nbr_d2 [n][k] float out (FP32 distances).
+ *   Invalid: NULL pointers, sizes out of range, unknown precision.
+ */
+int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t precision, int32_t n_cand,
+             int32_t* nbr_idx, float* nbr_d2, void* workspace, size_t* workspace_bytes, void* stream);
+
+/*
+ * tsne_calibrate_P -- perplexity calibration [vdMH08 eq. 1 and eq. 3].
+ * Per row i, over its k neighbour distances (FP32 arithmetic throughout):
+ * s_j = d_ij - min_l d_il, p_{j|i} = exp(-beta_i s_j) / sum_l exp(-beta_i s_l),
+ * with beta_i found by bisection (start 1, bracket (0, inf), doubling until
+ * bracketed) so that the entropy H = ln sum_l e^{-beta s_l} + beta sum_j p_j s_j
+ * equals ln(perplexity) nats to within tol.  Rows that do not reach it in
+ * max_iter evaluations (e.g. all k distances equal) keep the last beta and
+ * get converged = 0.
+ *
+ *   nbr_d2     [n][k] float, read-only (any order within a row).
+ *   perplexity 0 < perplexity < k.   tol > 0.   max_iter >= 1.
+ *   P_cond     [n][k] float out, aligned with nbr_d2; rows sum to 1.
+ *   beta       [n] float out (nullable).  converged [n] uint8 out (nullable).
+ *   n_unconverged  device int32 scalar out (nullable): rows with converged 0.
+ */
+int tsne_calibrate_P(const float* nbr_d2, int64_t n, int32_t k, float perplexity, float tol, int32_t max_iter,
+                     float* P_cond, float* beta, uint8_t* converged, int32_t* n_unconverged, void* stream);
+
+/*
+ * tsne_symmetrize -- symmetric joint probabilities [vdMH08 Sec. 3.1] on the
+ * kNN pattern [vdM14 Sec. 4.1]: with C_ij = p_{j|i} for j in N(i) (else 0),
+ * P = (C + C^T) / (2n).  Output is CSR over the union pattern with columns
+ * ascending and no diagonal; val[(i,j)] == val[(j,i)] bitwise.
+ *
+ *   nbr_idx  [n][k] int32, read-only: k distinct indices != i per row.
+ *   P_cond   [n][k] float, read-only, aligned with nbr_idx.
+ *   row_ptr  [n+1] int64 out.
+ *   col, val [2 n k] capacity, int32 / float out; the first nnz are used.
+ *   tpos     [2 n k] capacity int32 out (nullable): tpos[e] = position of
+ *            (j, i) for entry e = (i, j).
+ *   nnz      device int64 scalar out: the entry count, or -1 when a
+ *            neighbour list holds an index out of range, self or a repeat
+ *            (the outputs are then unspecified).
+ */
+int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64_t n, int32_t k, int64_t* row_ptr,
+                    int32_t* col, float* val, int32_t* tpos, int64_t* nnz, void* workspace, size_t* workspace_bytes,
+                    void* stream);
+
+/*
+ * tsne_kl_grad -- the exact t-SNE gradient [vdMH08 eq. 4 and eq. 5] with
+ * early exaggeration alpha [vdMH08 Sec. 3.4], all pairs evaluated:
+ *   w_ij = 1 / (1 + ||y_i - y_j||^2),  Z = sum over ordered i != j of w_ij,
+ *   g_i  = 4 sum_{j != i} (alpha p_ij - w_ij / Z) w_ij (y_i - y_j)
+ *        = 4 alpha sum_{e in row i} p_e w_e (y_i - y_j) - (4/Z) sum_{j != i} w_ij^2 (y_i - y_j).
+ * P must be symmetric (as tsne_symmetrize produces); Q is never stored.
+ * Pair terms are FP32; per-thread partial sums are folded into FP64 per
+ * tile and reduced in a fixed order.
+ *
+ *   Y        [n][2] float (interleaved x, y), read-only.   n >= 2.
+ *   row_ptr [n+1] int64, col [nnz] int32, val [nnz] float: P as CSR.
+ *   exaggeration alpha (> 0); applies to the attractive term only.
+ *   grad     [n][2] float out.
+ *   Z        device double scalar out (nullable).
+ *   kl       device double scalar out (nullable): KL(P||Q) =
+ *            sum_e p_e ln p_e - sum_e p_e ln w_e + (sum_e p_e) ln Z, always
+ *            with the un-exaggerated P (0 ln 0 = 0).
+ *   Zrow     [n] double out (nullable): per-row sums Z_i = sum_{j != i} w_ij.
+ */
+int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
+                 float exaggeration, float* grad, double* Z, double* kl, double* Zrow, void* workspace,
+                 size_t* workspace_bytes, void* stream);
+
+/*
+ * tsne_step -- one optimiser step, gradient descent with momentum
+ * [vdMH08 Algorithm 1] and adaptive gains [Jac88], elementwise over the 2n
+ * coordinates, in place, FP32:
+ *   gain  <- (grad * update < 0) ? gain + gain_inc : gain * gain_dec
+ *   gain  <- max(gain, min_gain)
+ *   update <- momentum * update - lr * gain * grad
+ *   Y     <- Y + update
+ *   Y, update, gains, grad  [n][2] float (grad read-only).
+ */
+int tsne_step(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr, float momentum,
+              float gain_inc, float gain_dec, float min_gain, void* stream);
+
+/*
+ * Differentiation form.  KL(P||Q) as a function of the embedding Y and of
+ * the stored values p_e of a CSR P whose pattern is symmetric (tpos valid);
+ * the values need be neither symmetric nor normalised:
+ *   C = sum_e p_e ln p_e - sum_e p_e ln w_e + S ln Z,   S = sum_e p_e,
+ * the KL of [vdMH08] eq. 2 written for stored entries.  Exact derivatives:
+ *   dC/dy_i = 2 sum_{e=(i,b)} p_e w_e (y_i - y_b) + 2 sum_{e=(a,i)} p_e w_e (y_i - y_a)
+ *             - (4 S / Z) sum_{j != i} w_ij^2 (y_i - y_j),
+ *   dC/dp_e = 1 + ln p_e - ln w_e + ln Z.
+ * The all-pairs terms are recomputed tile by tile (Q is never stored).
+ * dtype TSNE_F32 or TSNE_F64 selects float or double for Y, val, C, gC, dY,
+ * dP (one templated kernel source).  Stored p_e must be > 0.
+ *
+ * tsne_kl_forward:  C device scalar out (dtype); Z device double out (nullable).
+ * tsne_kl_backward: gC device scalar (dtype) in; dY [n][2] out; dP [nnz] out
+ *                   (nullable), both scaled by gC.
+ */
+int tsne_kl_forward(int32_t dtype, const void* Y, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                    const void* val, void* C, double* Z, void* workspace, size_t* workspace_bytes, void* stream);
+int tsne_kl_backward(int32_t dtype, const void* Y, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                     const void* val, const int32_t* tpos, const void* gC, void* dY, void* dP, void* workspace,
+                     size_t* workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSNE_MI355X_H */

@@ -1,0 +1,211 @@
+"""Torch-tensor front end of the C ABI (argument marshalling only).
+
+Each function checks dtype, device and contiguity, pulls raw device
+pointers and torch's current HIP stream, sizes the workspace with the
+library's query idiom and calls the entry point of the same name.  Every
+computation happens in the HIP kernels.  Nothing here synchronises except
+`symmetrize`, which reads the entry count back to size its outputs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+__all__ = ["knn", "calibrate_P", "symmetrize", "kl_grad", "step", "kl_forward", "kl_backward", "SparseP",
+           "Workspace"]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _req(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Workspace:
+    """Grow-only device scratch buffer reused across calls (one per owner)."""
+
+    def __init__(self, device=None):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+def _run_with_workspace(name, fn, args_before, args_after, device, ws: Workspace | None):
+    need = C.c_size_t(0)
+    check(name, fn(*args_before, None, C.byref(need), *args_after))
+    buf = (ws or Workspace()).get(need.value, device)
+    have = C.c_size_t(buf.numel())
+    check(name, fn(*args_before, _ptr(buf), C.byref(have), *args_after))
+    return buf
+
+
+def knn(X: torch.Tensor, k: int, precision: str = "fp32", n_cand: int | None = None, ws: Workspace | None = None):
+    """Exact kNN of the rows of X [n, d] float32.  Returns (idx int32 [n, k], d2 float32 [n, k])."""
+    _req(X, "X", torch.float32)
+    if X.dim() != 2:
+        raise ValueError("X must be [n, d]")
+    n, d = X.shape
+    prec = {"fp32": _lib.TSNE_KNN_FP32, "bf16": _lib.TSNE_KNN_BF16}[precision]
+    if n_cand is None:
+        n_cand = min(2 * k, n - 1) if precision == "bf16" else 0
+    idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    L = _lib.load()
+    _run_with_workspace("tsne_knn", L.tsne_knn, (_ptr(X), n, d, k, prec, n_cand, _ptr(idx), _ptr(d2)),
+                        (_stream(X.device),), X.device, ws)
+    return idx, d2
+
+
+def calibrate_P(nbr_d2: torch.Tensor, perplexity: float, tol: float = 1e-5, max_iter: int = 200):
+    """Per-row beta with entropy ln(perplexity).  Returns (P_cond, beta, converged, n_unconverged[1] int32)."""
+    _req(nbr_d2, "nbr_d2", torch.float32)
+    n, k = nbr_d2.shape
+    dev = nbr_d2.device
+    P = torch.empty((n, k), dtype=torch.float32, device=dev)
+    beta = torch.empty(n, dtype=torch.float32, device=dev)
+    conv = torch.empty(n, dtype=torch.uint8, device=dev)
+    nun = torch.empty(1, dtype=torch.int32, device=dev)
+    L = _lib.load()
+    check("tsne_calibrate_P", L.tsne_calibrate_P(_ptr(nbr_d2), n, k, float(perplexity), float(tol), int(max_iter),
+                                                 _ptr(P), _ptr(beta), _ptr(conv), _ptr(nun), _stream(dev)))
+    return P, beta, conv, nun
+
+
+@dataclass
+class SparseP:
+    """Symmetric P as CSR: row_ptr int64 [n+1], col int32 [nnz], val float32 [nnz], tpos int32 [nnz]."""
+
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+    tpos: torch.Tensor | None
+    n: int
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+
+def symmetrize(nbr_idx: torch.Tensor, P_cond: torch.Tensor, want_tpos: bool = True,
+               ws: Workspace | None = None) -> SparseP:
+    """P = (C + C^T) / (2n) on the union pattern (one host sync to read nnz)."""
+    _req(nbr_idx, "nbr_idx", torch.int32)
+    n, k = nbr_idx.shape
+    _req(P_cond, "P_cond", torch.float32, (n, k))
+    dev = nbr_idx.device
+    cap = 2 * n * k
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(cap, dtype=torch.int32, device=dev)
+    val = torch.empty(cap, dtype=torch.float32, device=dev)
+    tpos = torch.empty(cap, dtype=torch.int32, device=dev) if want_tpos else None
+    nnz = torch.empty(1, dtype=torch.int64, device=dev)
+    L = _lib.load()
+    _run_with_workspace("tsne_symmetrize", L.tsne_symmetrize,
+                        (_ptr(nbr_idx), _ptr(P_cond), n, k, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(tpos),
+                         _ptr(nnz)), (_stream(dev),), dev, ws)
+    m = int(nnz.item())
+    if m < 0:
+        raise ValueError("tsne_symmetrize: a neighbour list holds an out-of-range index, self or a repeat")
+    return SparseP(row_ptr, col[:m], val[:m], None if tpos is None else tpos[:m], n)
+
+
+def kl_grad(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, grad: torch.Tensor | None = None,
+            want_Z: bool = False, want_kl: bool = False, want_Zrow: bool = False, ws: Workspace | None = None):
+    """Exact t-SNE gradient.  Returns (grad [n, 2] f32, Z f64[1] or None, KL f64[1] or None, Zrow f64[n] or None)."""
+    _req(Y, "Y", torch.float32)
+    n = Y.shape[0]
+    if Y.shape != (n, 2) or P.n != n:
+        raise ValueError("Y must be [n, 2] matching P")
+    dev = Y.device
+    if grad is None:
+        grad = torch.empty_like(Y)
+    else:
+        _req(grad, "grad", torch.float32, (n, 2))
+    Z = torch.empty(1, dtype=torch.float64, device=dev) if want_Z else None
+    kl = torch.empty(1, dtype=torch.float64, device=dev) if want_kl else None
+    Zrow = torch.empty(n, dtype=torch.float64, device=dev) if want_Zrow else None
+    L = _lib.load()
+    _run_with_workspace("tsne_kl_grad", L.tsne_kl_grad,
+                        (_ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val), float(exaggeration), _ptr(grad),
+                         _ptr(Z), _ptr(kl), _ptr(Zrow)), (_stream(dev),), dev, ws)
+    return grad, Z, kl, Zrow
+
+
+def step(Y, update, gains, grad, lr: float, momentum: float, gain_inc: float = 0.2, gain_dec: float = 0.8,
+         min_gain: float = 0.01):
+    """In-place momentum + gains step on [n, 2] float32 tensors."""
+    n = Y.shape[0]
+    for t, name in ((Y, "Y"), (update, "update"), (gains, "gains"), (grad, "grad")):
+        _req(t, name, torch.float32, (n, 2))
+    L = _lib.load()
+    check("tsne_step", L.tsne_step(_ptr(Y), _ptr(update), _ptr(gains), _ptr(grad), n, float(lr), float(momentum),
+                                   float(gain_inc), float(gain_dec), float(min_gain), _stream(Y.device)))
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return _lib.TSNE_F32
+    if t.dtype == torch.float64:
+        return _lib.TSNE_F64
+    raise TypeError("only float32 and float64 are supported")
+
+
+def kl_forward(Y: torch.Tensor, val: torch.Tensor, P: SparseP, ws: Workspace | None = None):
+    """C = KL(P||Q) for stored values `val` on P's pattern.  Returns (C 0-d tensor, Z f64[1])."""
+    dt = _dtype_code(Y)
+    n = Y.shape[0]
+    _req(Y, "Y", Y.dtype, (n, 2))
+    _req(val, "val", Y.dtype, (P.nnz,))
+    dev = Y.device
+    Cout = torch.empty((), dtype=Y.dtype, device=dev)
+    Z = torch.empty(1, dtype=torch.float64, device=dev)
+    L = _lib.load()
+    _run_with_workspace("tsne_kl_forward", L.tsne_kl_forward,
+                        (dt, _ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(val), _ptr(Cout), _ptr(Z)),
+                        (_stream(dev),), dev, ws)
+    return Cout, Z
+
+
+def kl_backward(Y: torch.Tensor, val: torch.Tensor, P: SparseP, gC: torch.Tensor, want_dP: bool = True,
+                ws: Workspace | None = None):
+    """(dC/dY * gC [n, 2], dC/dp * gC [nnz] or None)."""
+    dt = _dtype_code(Y)
+    n = Y.shape[0]
+    _req(Y, "Y", Y.dtype, (n, 2))
+    _req(val, "val", Y.dtype, (P.nnz,))
+    if P.tpos is None:
+        raise ValueError("kl_backward needs P.tpos")
+    gC = gC.reshape(()).to(dtype=Y.dtype).contiguous()
+    dev = Y.device
+    dY = torch.empty_like(Y)
+    dP = torch.empty_like(val) if want_dP else None
+    L = _lib.load()
+    _run_with_workspace("tsne_kl_backward", L.tsne_kl_backward,
+                        (dt, _ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(val), _ptr(P.tpos), _ptr(gC), _ptr(dY),
+                         _ptr(dP)), (_stream(dev),), dev, ws)
+    return dY, dP

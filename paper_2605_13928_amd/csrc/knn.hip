@@ -1,0 +1,391 @@
+// tsne_knn: exact k nearest neighbours by squared Euclidean distance
+// (the kNN input of tree-accelerated t-SNE, van der Maaten 2014, Sec. 4.1),
+// in two precisions:
+//   FP32  -- distances as FP32 direct differences on the VALU;
+//   BF16  -- distances between bf16-rounded points from MFMA tiles
+//            (v_mfma_f32_16x16x32_bf16, FP32 accumulation; the norms ride
+//            in spare K slots, so the tile output IS the distance), the
+//            n_cand best per row kept, then re-ranked by FP32 direct
+//            differences on the original points.
+// Selection (both paths): every row owns a candidate buffer in global
+// memory, a count and a threshold tau in LDS.  A candidate with d <= tau is
+// appended (LDS atomic for the slot).  Before a buffer could overflow, the
+// owning wave sorts it (wave-wide bitonic sort of (d, j) keys), keeps the
+// best k and sets tau to the k-th distance.  The true k best always satisfy
+// d <= tau, so nothing is lost; ties at tau are kept and resolved by index
+// in the final sort.
+#include "common.hpp"
+
+namespace tsne {
+
+// ---------------------------------------------------------------------
+// Candidate buffers.
+
+template <int EPL>
+__device__ void compact_row(uint64_t* __restrict__ buf, int* cnt, float* tau, int keep) {
+  const int lane = lane_id();
+  __threadfence();  // earlier appends of this wave visible to the loads below
+  const int c = *cnt;
+  uint64_t v[EPL];
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int e = t * 64 + lane;
+    v[t] = e < c ? buf[e] : KEY_MAX;
+  }
+  wave_sort<EPL>(v);
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int e = t * 64 + lane;
+    if (e < keep) buf[e] = v[t];
+  }
+  float nt = INFINITY;
+  if (c >= keep) nt = key_dist(wave_pick<EPL>(v, keep - 1));
+  __threadfence();
+  if (lane == 0) {
+    *cnt = c < keep ? c : keep;
+    *tau = nt;
+  }
+}
+
+// Sort a row's buffer and write its first `keep` keys out.
+template <int EPL>
+__device__ void emit_row(const uint64_t* __restrict__ buf, int c, int keep, int32_t* __restrict__ oidx,
+                         float* __restrict__ od2) {
+  const int lane = lane_id();
+  __threadfence();
+  uint64_t v[EPL];
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int e = t * 64 + lane;
+    v[t] = e < c ? buf[e] : KEY_MAX;
+  }
+  wave_sort<EPL>(v);
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int e = t * 64 + lane;
+    if (e < keep) {
+      oidx[e] = key_index(v[t]);
+      if (od2) od2[e] = key_dist(v[t]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
+// FP32 exact path.  Block = 4 waves x 16 rows; each step covers 128
+// columns, 2 per lane; the rows' coordinates are LDS broadcasts, the
+// columns' are per-lane LDS reads, dimension chunks of 64.
+
+constexpr int F_RW = 16;
+constexpr int F_ROWS = 64;
+constexpr int F_COLS = 128;
+constexpr int F_DC = 64;
+
+template <int EPL>
+__global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__ X, int64_t n, int d, int k,
+                                                       uint64_t* __restrict__ bufs, int32_t* __restrict__ out_idx,
+                                                       float* __restrict__ out_d2) {
+  constexpr int CAP = 64 * EPL;
+  __shared__ __attribute__((aligned(16))) float xi_s[F_DC][F_ROWS];
+  __shared__ __attribute__((aligned(16))) float xj_s[F_DC][F_COLS];
+  __shared__ int cnt_s[F_ROWS];
+  __shared__ float tau_s[F_ROWS];
+  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int64_t row0 = int64_t(blockIdx.x) * F_ROWS;
+  if (tid < F_ROWS) {
+    cnt_s[tid] = 0;
+    tau_s[tid] = INFINITY;
+  }
+  for (int64_t c0 = 0; c0 < n; c0 += F_COLS) {
+    float acc[F_RW][2];
+#pragma unroll
+    for (int r = 0; r < F_RW; ++r) acc[r][0] = acc[r][1] = 0.0f;
+    for (int dc = 0; dc < d; dc += F_DC) {
+      const int dl = (d - dc) < F_DC ? (d - dc) : F_DC;
+      __syncthreads();
+      for (int u = tid; u < F_ROWS * dl; u += 256) {
+        const int r = u / dl, c = u - r * dl;
+        const int64_t g = row0 + r;
+        xi_s[c][r] = g < n ? X[g * d + dc + c] : 0.0f;
+      }
+      for (int u = tid; u < F_COLS * dl; u += 256) {
+        const int jj = u / dl, c = u - jj * dl;
+        const int64_t g = c0 + jj;
+        xj_s[c][jj] = g < n ? X[g * d + dc + c] : 0.0f;
+      }
+      __syncthreads();
+      for (int c = 0; c < dl; ++c) {
+        const float4* ap = reinterpret_cast<const float4*>(&xi_s[c][w * F_RW]);
+        const float4 a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
+        const float a[F_RW] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
+                               a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
+        const float2 b = *reinterpret_cast<const float2*>(&xj_s[c][lane * 2]);
+#pragma unroll
+        for (int r = 0; r < F_RW; ++r) {
+          const float t0 = a[r] - b.x, t1 = a[r] - b.y;
+          acc[r][0] = __builtin_fmaf(t0, t0, acc[r][0]);
+          acc[r][1] = __builtin_fmaf(t1, t1, acc[r][1]);
+        }
+      }
+    }
+    // filter + append
+#pragma unroll
+    for (int r = 0; r < F_RW; ++r) {
+      const int lr = w * F_RW + r;
+      const int64_t gi = row0 + lr;
+      const float tau = tau_s[lr];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int64_t j = c0 + lane * 2 + u;
+        const float dd = acc[r][u];
+        if (gi < n && j < n && j != gi && dd <= tau) {
+          const int pos = atomicAdd(&cnt_s[lr], 1);
+          bufs[gi * CAP + pos] = make_key(dd, int32_t(j));
+        }
+      }
+    }
+    // compaction of rows that could overflow in the next step
+    const int cl = lane < F_RW ? cnt_s[w * F_RW + lane] : 0;
+    uint64_t need = __ballot(lane < F_RW && cl > CAP - F_COLS);
+    while (need) {
+      const int r = __ffsll((unsigned long long)need) - 1;
+      need &= need - 1;
+      const int lr = w * F_RW + r;
+      compact_row<EPL>(bufs + (row0 + lr) * CAP, &cnt_s[lr], &tau_s[lr], k);
+    }
+  }
+  for (int r = 0; r < F_RW; ++r) {
+    const int lr = w * F_RW + r;
+    const int64_t gi = row0 + lr;
+    if (gi >= n) break;
+    emit_row<EPL>(bufs + gi * CAP, cnt_s[lr], k, out_idx + gi * k, out_d2 + gi * k);
+  }
+}
+
+// ---------------------------------------------------------------------
+// BF16 path.
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+constexpr uint16_t BF16_ONE = 0x3F80;
+
+// One wave per row.  Query row:     [x~ (d), nh, nm, nl, 1, 1, 1, 0 ...]
+//                   candidate row:  [-2 x~ (d), 1, 1, 1, nh, nm, nl, 0 ...]
+// so that <query_i, candidate_j> = |x~_i|^2 + |x~_j|^2 - 2 <x~_i, x~_j>, the
+// squared distance of the rounded points; |x~|^2 (FP32) is carried as the
+// sum nh + nm + nl of three bf16 parts.
+__global__ __launch_bounds__(256) void bf16_prep_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                        uint16_t* __restrict__ Xq, uint16_t* __restrict__ Xc) {
+  const int lane = lane_id();
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const bool has = lane < d;
+  const uint16_t h = has ? bf16_rne(X[row * d + lane]) : uint16_t(0);
+  const float xr = bf16_to_f(h);
+  const float nrm = wave_sum(xr * xr);
+  const uint16_t nh = bf16_rne(nrm);
+  const float r1 = nrm - bf16_to_f(nh);
+  const uint16_t nm = bf16_rne(r1);
+  const float r2 = r1 - bf16_to_f(nm);
+  const uint16_t nl = bf16_rne(r2);
+  uint16_t q = 0, c = 0;
+  if (has) {
+    q = h;
+    c = bf16_rne(-2.0f * xr);  // exact: scaling by -2 keeps the 8-bit significand
+  } else if (lane < d + 3) {
+    const int t = lane - d;
+    q = t == 0 ? nh : (t == 1 ? nm : nl);
+    c = BF16_ONE;
+  } else if (lane < d + 6) {
+    const int t = lane - d - 3;
+    q = BF16_ONE;
+    c = t == 0 ? nh : (t == 1 ? nm : nl);
+  }
+  Xq[row * 64 + lane] = q;
+  Xc[row * 64 + lane] = c;
+}
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+constexpr int B_TJ = 64;  // candidates per LDS tile
+
+template <int EPL>
+__global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
+                                                       int64_t n, int ncand, uint64_t* __restrict__ bufs,
+                                                       int32_t* __restrict__ cand) {
+  constexpr int CAP = 64 * EPL;
+  __shared__ uint4 tile[B_TJ * 8];  // 64 rows x 128 bytes
+  __shared__ int cnt_s[256];
+  __shared__ float tau_s[256];
+  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int64_t qbase = int64_t(blockIdx.x) * 256 + w * 64;
+  cnt_s[tid] = 0;
+  tau_s[tid] = INFINITY;
+  // query fragments: tile t, k-step s; lane holds query qbase + 16 t + lane % 16,
+  // k elements 32 s + 8 (lane / 16) ... + 7
+  bf16x8_t bq[4][2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t qi = qbase + t * 16 + (lane & 15);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (qi < n) v = Xq[qi * 8 + s * 4 + (lane >> 4)];
+      bq[t][s] = __builtin_bit_cast(bf16x8_t, v);
+    }
+  }
+  float tau[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  for (int64_t c0 = 0; c0 < n; c0 += B_TJ) {
+    __syncthreads();
+    for (int u = tid; u < B_TJ * 8; u += 256) {
+      const int64_t g = c0 + (u >> 3);
+      tile[u] = g < n ? Xc[g * 8 + (u & 7)] : make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sub = 0; sub < B_TJ / 16; ++sub) {
+      const int rloc = sub * 16 + (lane & 15);
+      const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, tile[rloc * 8 + (lane >> 4)]);
+      const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, tile[rloc * 8 + 4 + (lane >> 4)]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        floatx4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bq[t][0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bq[t][1], acc, 0, 0, 0);
+        // acc[r] = distance(query qbase + 16 t + lane % 16, candidate c0 + 16 sub + 4 (lane / 16) + r)
+        const int64_t qi = qbase + t * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t j = c0 + sub * 16 + 4 * (lane >> 4) + r;
+          const float dd = acc[r];
+          if (dd <= tau[t] && j < n && j != qi && qi < n) {
+            const int lq = w * 64 + t * 16 + (lane & 15);
+            const int pos = atomicAdd(&cnt_s[lq], 1);
+            bufs[qi * CAP + pos] = make_key(fmaxf(dd, 0.0f), int32_t(j));
+          }
+        }
+      }
+    }
+    const int cl = cnt_s[w * 64 + lane];
+    uint64_t need = __ballot(cl > CAP - B_TJ);
+    if (need) {
+      while (need) {
+        const int r = __ffsll((unsigned long long)need) - 1;
+        need &= need - 1;
+        const int lq = w * 64 + r;
+        compact_row<EPL>(bufs + (qbase + r) * CAP, &cnt_s[lq], &tau_s[lq], ncand);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) tau[t] = tau_s[w * 64 + t * 16 + (lane & 15)];
+    }
+  }
+  for (int r = 0; r < 64; ++r) {
+    const int64_t qi = qbase + r;
+    if (qi >= n) break;
+    emit_row<EPL>(bufs + qi * CAP, cnt_s[w * 64 + r], ncand, cand + qi * ncand, nullptr);
+  }
+}
+
+// Re-rank: one wave per row; FP32 direct differences (same arithmetic as the
+// FP32 path) of the row's candidates, sorted by (d, j); best k written.
+__global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                     const int32_t* __restrict__ cand, int ncand, int k,
+                                                     int32_t* __restrict__ out_idx, float* __restrict__ out_d2) {
+  const int lane = lane_id();
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const float* xi = X + row * d;
+  uint64_t v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = t * 64 + lane;
+    v[t] = KEY_MAX;
+    const int32_t j = e < ncand ? cand[row * ncand + e] : -1;
+    if (j >= 0 && j < n) {  // a row short of candidates (non-finite input) holds -1
+      const float* xj = X + int64_t(j) * d;
+      float s = 0.0f;
+      for (int c = 0; c < d; ++c) {
+        const float u = xi[c] - xj[c];
+        s = __builtin_fmaf(u, u, s);
+      }
+      v[t] = make_key(s, j);
+    }
+  }
+  wave_sort<4>(v);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = t * 64 + lane;
+    if (e < k) {
+      out_idx[row * k + e] = key_index(v[t]);
+      out_d2[row * k + e] = key_dist(v[t]);
+    }
+  }
+}
+
+struct KnnLayout {
+  int epl;
+  size_t o_buf, o_xq, o_xc, o_cand, bytes;
+  static KnnLayout make(int64_t n, int k, int precision, int ncand) {
+    KnnLayout L;
+    Carve c;
+    if (precision == TSNE_KNN_FP32) {
+      L.epl = k <= 128 ? 4 : 8;
+      L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * size_t(64 * L.epl));
+      L.o_xq = L.o_xc = L.o_cand = 0;
+    } else {
+      L.epl = 8;  // capacity 512, headroom 64 per tile
+      L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * 512);
+      L.o_xq = c.take(sizeof(uint16_t) * size_t(n) * 64);
+      L.o_xc = c.take(sizeof(uint16_t) * size_t(n) * 64);
+      L.o_cand = c.take(sizeof(int32_t) * size_t(n) * size_t(ncand));
+    }
+    L.bytes = c.off;
+    return L;
+  }
+};
+
+}  // namespace tsne
+
+extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t precision, int32_t n_cand,
+                        int32_t* nbr_idx, float* nbr_d2, void* workspace, size_t* workspace_bytes, void* stream) {
+  using namespace tsne;
+  if (!X || !nbr_idx || !nbr_d2 || n < 2 || d < 1 || k < 1 || k >= n) return TSNE_ERR_INVALID_ARG;
+  if (precision != TSNE_KNN_FP32 && precision != TSNE_KNN_BF16) return TSNE_ERR_INVALID_ARG;
+  if (precision == TSNE_KNN_BF16 && (n_cand < k || n_cand >= n)) return TSNE_ERR_INVALID_ARG;
+  if (k > TSNE_MAX_K || d > TSNE_MAX_D) return TSNE_ERR_UNSUPPORTED;
+  if (precision == TSNE_KNN_BF16 && (n_cand > TSNE_MAX_K || d > TSNE_MAX_D_BF16)) return TSNE_ERR_UNSUPPORTED;
+  if (n > (int64_t(1) << 31) - 1) return TSNE_ERR_UNSUPPORTED;
+  const KnnLayout L = KnnLayout::make(n, k, precision, n_cand);
+  int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
+  if (rc >= 0) return rc;
+  char* ws = static_cast<char*>(workspace);
+  uint64_t* bufs = reinterpret_cast<uint64_t*>(ws + L.o_buf);
+  hipStream_t s = as_stream(stream);
+  if (precision == TSNE_KNN_FP32) {
+    const dim3 grid(unsigned(ceil_div(n, F_ROWS)));
+    if (L.epl == 4)
+      hipLaunchKernelGGL(knn_fp32_kernel<4>, grid, dim3(256), 0, s, X, n, d, k, bufs, nbr_idx, nbr_d2);
+    else
+      hipLaunchKernelGGL(knn_fp32_kernel<8>, grid, dim3(256), 0, s, X, n, d, k, bufs, nbr_idx, nbr_d2);
+    TSNE_CHECK_LAUNCH();
+    return TSNE_OK;
+  }
+  uint16_t* Xq = reinterpret_cast<uint16_t*>(ws + L.o_xq);
+  uint16_t* Xc = reinterpret_cast<uint16_t*>(ws + L.o_xc);
+  int32_t* cand = reinterpret_cast<int32_t*>(ws + L.o_cand);
+  hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, Xq, Xc);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(knn_bf16_kernel<8>, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
+                     reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), n, n_cand, bufs, cand);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(rerank_kernel, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, cand, n_cand, k, nbr_idx,
+                     nbr_d2);
+  TSNE_CHECK_LAUNCH();
+  return TSNE_OK;
+}

@@ -1,0 +1,392 @@
+// tsne_symmetrize: P = (C + C^T) / (2n) on the union of the kNN patterns
+// (van der Maaten & Hinton 2008, Sec. 3.1; sparse pattern as in van der
+// Maaten 2014, Sec. 4.1), as CSR with ascending columns plus the transpose
+// positions.  HBM-bound integer work, deterministic:
+//   1. in-degree histogram (integer atomics), exclusive scan -> in_ptr
+//   2. scatter (source, p) into the transposed lists (atomic cursors give an
+//      arbitrary order) ...
+//   3. ... which a per-row rank sort (one wave per row) makes canonical
+//   4. rank-sort each row's k out-entries by column
+//   5. union size per row (binary search of each out-entry in the in-list),
+//      scan -> row_ptr
+//   6. merge by ranks: position of an element = its rank in its own list +
+//      its rank in the other list - the shared entries before it
+//   7. tpos by binary search of i in row col[e]
+// Entry values are (p_{j|i} + p_{i|j}) / (2n) in row i and
+// (p_{i|j} + p_{j|i}) / (2n) in row j: the same FP32 sum, so P = P^T bitwise.
+#include "common.hpp"
+
+namespace tsne {
+
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = 256 * SCAN_ITEMS;
+
+template <typename TIn>
+__global__ __launch_bounds__(256) void scan_chunk_sums(const TIn* __restrict__ in, int64_t n, int64_t* __restrict__ bsum) {
+  __shared__ double red_unused[1];
+  __shared__ int64_t part[256];
+  (void)red_unused;
+  const int64_t base = int64_t(blockIdx.x) * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
+  int64_t s = 0;
+#pragma unroll
+  for (int t = 0; t < SCAN_ITEMS; ++t)
+    if (base + t < n) s += int64_t(in[base + t]);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = part[0];
+}
+
+// Exclusive scan of nb chunk sums in place by one block; bsum[nb] = total.
+__global__ __launch_bounds__(256) void scan_chunk_prefix(int64_t* __restrict__ bsum, int64_t nb) {
+  __shared__ int64_t buf[256];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+    const int64_t b = b0 + threadIdx.x;
+    const int64_t v = b < nb ? bsum[b] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      int64_t add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (b < nb) bsum[b] = carry + buf[threadIdx.x] - v;
+    const int64_t tot = buf[255];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+// out[t] = sum_{u < t} in[u] for t = 0..n (out has n + 1 entries).
+template <typename TIn>
+__global__ __launch_bounds__(256) void scan_apply(const TIn* __restrict__ in, int64_t n,
+                                                  const int64_t* __restrict__ bsum, int64_t nb,
+                                                  int64_t* __restrict__ out) {
+  __shared__ int64_t buf[256];
+  const int64_t base = int64_t(blockIdx.x) * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
+  int64_t v[SCAN_ITEMS];
+  int64_t s = 0;
+#pragma unroll
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    v[t] = (base + t < n) ? int64_t(in[base + t]) : 0;
+    s += v[t];
+  }
+  buf[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int64_t add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+    __syncthreads();
+    buf[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t run = bsum[blockIdx.x] + buf[threadIdx.x] - s;
+#pragma unroll
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    if (base + t < n) out[base + t] = run;
+    run += v[t];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[nb];
+}
+
+template <typename TIn>
+int exclusive_scan(const TIn* in, int64_t n, int64_t* out, int64_t* bsum, hipStream_t s) {
+  const int64_t nb = ceil_div(n, SCAN_CHUNK);
+  hipLaunchKernelGGL(scan_chunk_sums<TIn>, dim3(unsigned(nb)), dim3(256), 0, s, in, n, bsum);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(scan_chunk_prefix, dim3(1), dim3(256), 0, s, bsum, nb);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(scan_apply<TIn>, dim3(unsigned(nb)), dim3(256), 0, s, in, n, bsum, nb, out);
+  TSNE_CHECK_LAUNCH();
+  return TSNE_OK;
+}
+
+__device__ __forceinline__ bool edge_ok(int64_t i, int32_t j, int64_t n) { return j >= 0 && j < n && j != i; }
+
+__global__ __launch_bounds__(256) void sym_indeg_kernel(const int32_t* __restrict__ nbr, int64_t n, int k,
+                                                        int* __restrict__ indeg, int* __restrict__ err) {
+  const int64_t e = gtid();
+  if (e >= n * k) return;
+  const int64_t i = e / k;
+  const int32_t j = nbr[e];
+  if (!edge_ok(i, j, n)) {
+    atomicOr(err, 1);
+    return;
+  }
+  atomicAdd(&indeg[j], 1);
+}
+
+__global__ __launch_bounds__(256) void sym_scatter_kernel(const int32_t* __restrict__ nbr,
+                                                          const float* __restrict__ Pc, int64_t n, int k,
+                                                          const int64_t* __restrict__ in_ptr, int* __restrict__ cursor,
+                                                          int32_t* __restrict__ in_src, float* __restrict__ in_val) {
+  const int64_t e = gtid();
+  if (e >= n * k) return;
+  const int64_t i = e / k;
+  const int32_t j = nbr[e];
+  if (!edge_ok(i, j, n)) return;
+  const int64_t pos = in_ptr[j] + atomicAdd(&cursor[j], 1);
+  in_src[pos] = int32_t(i);
+  in_val[pos] = Pc[e];
+}
+
+// Stable rank sort of one segment per wave: element e goes to position
+// #{f : key_f < key_e} + #{f < e : key_f == key_e}, a permutation even when
+// keys repeat (repeats are reported through err).
+__device__ void wave_rank_sort_segment(const int32_t* __restrict__ key, const float* __restrict__ val, int64_t len,
+                                       int32_t* __restrict__ okey, float* __restrict__ oval, int* __restrict__ err) {
+  const int lane = lane_id();
+  for (int64_t b0 = 0; b0 < len; b0 += 256) {
+    int32_t mk[4];
+    int64_t rank[4];
+    bool own[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t e = b0 + lane + 64 * t;
+      own[t] = e < len;
+      mk[t] = own[t] ? key[e] : 0;
+      rank[t] = 0;
+    }
+    bool rep = false;
+    for (int64_t f = 0; f < len; ++f) {
+      const int32_t kf = key[f];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t e = b0 + lane + 64 * t;
+        const bool eq = kf == mk[t];
+        rank[t] += (kf < mk[t]) || (eq && f < e);
+        rep |= own[t] && eq && f != e;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (!own[t]) continue;
+      const int64_t e = b0 + lane + 64 * t;
+      okey[rank[t]] = mk[t];
+      oval[rank[t]] = val[e];
+    }
+    if (rep) atomicOr(err, 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void sym_sort_in_kernel(const int64_t* __restrict__ in_ptr,
+                                                          const int32_t* __restrict__ in_src,
+                                                          const float* __restrict__ in_val, int64_t n,
+                                                          int32_t* __restrict__ s_src, float* __restrict__ s_val,
+                                                          int* __restrict__ err) {
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t a = in_ptr[row], b = in_ptr[row + 1];
+  wave_rank_sort_segment(in_src + a, in_val + a, b - a, s_src + a, s_val + a, err);
+}
+
+__global__ __launch_bounds__(256) void sym_sort_out_kernel(const int32_t* __restrict__ nbr,
+                                                           const float* __restrict__ Pc, int64_t n, int k,
+                                                           int32_t* __restrict__ o_col, float* __restrict__ o_val,
+                                                           int* __restrict__ err) {
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t a = row * k;
+  wave_rank_sort_segment(nbr + a, Pc + a, k, o_col + a, o_val + a, err);
+}
+
+// First position in sorted[0..len) whose value is >= x.
+__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* __restrict__ sorted, int64_t len, int32_t x) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (sorted[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void sym_union_count_kernel(int64_t n, int k, const int32_t* __restrict__ o_col,
+                                                              const int64_t* __restrict__ in_ptr,
+                                                              const int32_t* __restrict__ s_src,
+                                                              int64_t* __restrict__ ucount) {
+  const int lane = lane_id();
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int32_t* in = s_src + in_ptr[row];
+  const int64_t len = in_ptr[row + 1] - in_ptr[row];
+  int dups = 0;
+  for (int a0 = 0; a0 < k; a0 += 64) {
+    const int a = a0 + lane;
+    bool dup = false;
+    if (a < k) {
+      const int32_t c = o_col[row * k + a];
+      const int64_t lb = lower_bound_i32(in, len, c);
+      dup = lb < len && in[lb] == c;
+    }
+    dups += __popcll(__ballot(dup));
+  }
+  if (lane == 0) ucount[row] = int64_t(k) + len - dups;
+}
+
+__global__ __launch_bounds__(256) void sym_write_kernel(int64_t n, int k, const int32_t* __restrict__ o_col,
+                                                        const float* __restrict__ o_val,
+                                                        const int64_t* __restrict__ in_ptr,
+                                                        const int32_t* __restrict__ s_src,
+                                                        const float* __restrict__ s_val,
+                                                        const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+                                                        float* __restrict__ val) {
+  const int lane = lane_id();
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const float two_n = 2.0f * float(n);
+  const int32_t* in = s_src + in_ptr[row];
+  const float* inv = s_val + in_ptr[row];
+  const int64_t len = in_ptr[row + 1] - in_ptr[row];
+  const int32_t* out = o_col + row * k;
+  const float* outv = o_val + row * k;
+  const int64_t rp = row_ptr[row];
+  const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+  // out-entries
+  int run = 0;
+  for (int a0 = 0; a0 < k; a0 += 64) {
+    const int a = a0 + lane;
+    bool dup = false;
+    int64_t lb = 0;
+    int32_t c = 0;
+    if (a < k) {
+      c = out[a];
+      lb = lower_bound_i32(in, len, c);
+      dup = lb < len && in[lb] == c;
+    }
+    const uint64_t m = __ballot(dup);
+    if (a < k) {
+      const int64_t pos = a + lb - (run + __popcll(m & lt_mask));
+      col[rp + pos] = c;
+      val[rp + pos] = (outv[a] + (dup ? inv[lb] : 0.0f)) / two_n;
+    }
+    run += __popcll(m);
+  }
+  // in-entries not shared with the out-list
+  run = 0;
+  for (int64_t b0 = 0; b0 < len; b0 += 64) {
+    const int64_t b = b0 + lane;
+    bool dup = false;
+    int64_t lb = 0;
+    int32_t c = 0;
+    if (b < len) {
+      c = in[b];
+      lb = lower_bound_i32(out, k, c);
+      dup = lb < k && out[lb] == c;
+    }
+    const uint64_t m = __ballot(dup);
+    if (b < len && !dup) {
+      const int64_t pos = b + lb - (run + __popcll(m & lt_mask));
+      col[rp + pos] = c;
+      val[rp + pos] = (0.0f + inv[b]) / two_n;
+    }
+    run += __popcll(m);
+  }
+}
+
+__global__ __launch_bounds__(256) void sym_tpos_kernel(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col, int32_t* __restrict__ tpos) {
+  const int lane = lane_id();
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  for (int64_t e = row_ptr[row] + lane; e < row_ptr[row + 1]; e += 64) {
+    const int32_t j = col[e];
+    int32_t t = -1;
+    if (j >= 0 && j < n) {
+      const int64_t a = row_ptr[j];
+      const int64_t lb = lower_bound_i32(col + a, row_ptr[j + 1] - a, int32_t(row));
+      t = int32_t(a + lb);
+    }
+    tpos[e] = t;
+  }
+}
+
+__global__ void sym_nnz_kernel(const int64_t* __restrict__ row_ptr, int64_t n, const int* __restrict__ err,
+                               int64_t* __restrict__ nnz) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *nnz = *err ? int64_t(-1) : row_ptr[n];
+}
+
+struct SymLayout {
+  size_t o_indeg, o_cursor, o_err, o_inptr, o_src, o_val, o_ssrc, o_sval, o_ocol, o_oval, o_ucount, o_bsum, bytes;
+  static SymLayout make(int64_t n, int k) {
+    SymLayout L;
+    const size_t nk = size_t(n) * size_t(k);
+    const size_t nb = size_t(ceil_div(n + 1, SCAN_CHUNK)) + 1;
+    Carve c;
+    L.o_indeg = c.take(sizeof(int) * size_t(n));
+    L.o_cursor = c.take(sizeof(int) * size_t(n));
+    L.o_err = c.take(sizeof(int));
+    L.o_inptr = c.take(sizeof(int64_t) * (size_t(n) + 1));
+    L.o_src = c.take(sizeof(int32_t) * nk);
+    L.o_val = c.take(sizeof(float) * nk);
+    L.o_ssrc = c.take(sizeof(int32_t) * nk);
+    L.o_sval = c.take(sizeof(float) * nk);
+    L.o_ocol = c.take(sizeof(int32_t) * nk);
+    L.o_oval = c.take(sizeof(float) * nk);
+    L.o_ucount = c.take(sizeof(int64_t) * size_t(n));
+    L.o_bsum = c.take(sizeof(int64_t) * nb);
+    L.bytes = c.off;
+    return L;
+  }
+};
+
+}  // namespace tsne
+
+extern "C" int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64_t n, int32_t k, int64_t* row_ptr,
+                               int32_t* col, float* val, int32_t* tpos, int64_t* nnz, void* workspace,
+                               size_t* workspace_bytes, void* stream) {
+  using namespace tsne;
+  if (!nbr_idx || !P_cond || !row_ptr || !col || !val || !nnz || n < 2 || k < 1 || k >= n) return TSNE_ERR_INVALID_ARG;
+  if (k > TSNE_MAX_K) return TSNE_ERR_UNSUPPORTED;
+  if (n > (int64_t(1) << 30)) return TSNE_ERR_UNSUPPORTED;  // 2 n k must fit int32 positions in tpos
+  if (2 * n * int64_t(k) > (int64_t(1) << 31) - 1) return TSNE_ERR_UNSUPPORTED;
+  const SymLayout L = SymLayout::make(n, k);
+  int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
+  if (rc >= 0) return rc;
+  char* ws = static_cast<char*>(workspace);
+  int* indeg = reinterpret_cast<int*>(ws + L.o_indeg);
+  int* cursor = reinterpret_cast<int*>(ws + L.o_cursor);
+  int* err = reinterpret_cast<int*>(ws + L.o_err);
+  int64_t* in_ptr = reinterpret_cast<int64_t*>(ws + L.o_inptr);
+  int32_t* in_src = reinterpret_cast<int32_t*>(ws + L.o_src);
+  float* in_val = reinterpret_cast<float*>(ws + L.o_val);
+  int32_t* s_src = reinterpret_cast<int32_t*>(ws + L.o_ssrc);
+  float* s_val = reinterpret_cast<float*>(ws + L.o_sval);
+  int32_t* o_col = reinterpret_cast<int32_t*>(ws + L.o_ocol);
+  float* o_val = reinterpret_cast<float*>(ws + L.o_oval);
+  int64_t* ucount = reinterpret_cast<int64_t*>(ws + L.o_ucount);
+  int64_t* bsum = reinterpret_cast<int64_t*>(ws + L.o_bsum);
+  hipStream_t s = as_stream(stream);
+  const int64_t nk = n * k;
+  const dim3 g_edges(unsigned(ceil_div(nk, 256))), g_rows(unsigned(ceil_div(n, 4))), b(256);
+
+  if ((rc = launch_fill<int>(indeg, n, 0, s))) return rc;
+  if ((rc = launch_fill<int>(cursor, n, 0, s))) return rc;
+  if ((rc = launch_fill<int>(err, 1, 0, s))) return rc;
+  hipLaunchKernelGGL(sym_indeg_kernel, g_edges, b, 0, s, nbr_idx, n, k, indeg, err);
+  TSNE_CHECK_LAUNCH();
+  if ((rc = exclusive_scan<int>(indeg, n, in_ptr, bsum, s))) return rc;
+  hipLaunchKernelGGL(sym_scatter_kernel, g_edges, b, 0, s, nbr_idx, P_cond, n, k, in_ptr, cursor, in_src, in_val);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(sym_sort_in_kernel, g_rows, b, 0, s, in_ptr, in_src, in_val, n, s_src, s_val, err);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(sym_sort_out_kernel, g_rows, b, 0, s, nbr_idx, P_cond, n, k, o_col, o_val, err);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(sym_union_count_kernel, g_rows, b, 0, s, n, k, o_col, in_ptr, s_src, ucount);
+  TSNE_CHECK_LAUNCH();
+  if ((rc = exclusive_scan<int64_t>(ucount, n, row_ptr, bsum, s))) return rc;
+  hipLaunchKernelGGL(sym_write_kernel, g_rows, b, 0, s, n, k, o_col, o_val, in_ptr, s_src, s_val, row_ptr, col, val);
+  TSNE_CHECK_LAUNCH();
+  if (tpos) {
+    hipLaunchKernelGGL(sym_tpos_kernel, g_rows, b, 0, s, n, row_ptr, col, tpos);
+    TSNE_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(sym_nnz_kernel, dim3(1), dim3(64), 0, s, row_ptr, n, err, nnz);
+  TSNE_CHECK_LAUNCH();
+  return TSNE_OK;
+}

@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every entry point the header declares, answers workspace queries and
+rejects invalid arguments before making any HIP call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2605_13928_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsne_mi355x.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsne_[a-zA-Z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+    assert L.tsne_abi_version() == 1
+    assert L.tsne_status_string(3).decode() == "workspace too small"
+
+
+NULL = None
+
+
+def ws_query(fn, *before, after=(NULL,)):
+    need = C.c_size_t(0)
+    rc = fn(*before, NULL, C.byref(need), *after)
+    return rc, need.value
+
+
+def test_workspace_queries_need_no_device(L):
+    fake = C.c_void_p(0x1000)
+    rc, need = ws_query(L.tsne_knn, fake, 20000, 50, 90, _lib.TSNE_KNN_FP32, 0, fake, fake)
+    assert rc == 0 and need >= 20000 * 256 * 8
+    rc, need_b = ws_query(L.tsne_knn, fake, 20000, 50, 90, _lib.TSNE_KNN_BF16, 180, fake, fake)
+    assert rc == 0 and need_b > need
+    rc, need = ws_query(L.tsne_symmetrize, fake, fake, 1000, 90, fake, fake, fake, fake, fake)
+    assert rc == 0 and need > 1000 * 90 * 4 * 6
+    rc, need = ws_query(L.tsne_kl_grad, fake, 1000, fake, fake, fake, C.c_float(12.0), fake, NULL, NULL, NULL)
+    assert rc == 0 and need > 0
+    for dt in (_lib.TSNE_F32, _lib.TSNE_F64):
+        rc, need = ws_query(L.tsne_kl_forward, dt, fake, 64, fake, fake, fake, fake, NULL)
+        assert rc == 0 and need > 0
+        rc, need = ws_query(L.tsne_kl_backward, dt, fake, 64, fake, fake, fake, fake, fake, fake, NULL)
+        assert rc == 0 and need > 0
+
+
+def test_too_small_workspace_is_rejected_before_launch(L):
+    fake = C.c_void_p(0x1000)
+    have = C.c_size_t(16)
+    rc = L.tsne_kl_grad(fake, 1000, fake, fake, fake, C.c_float(1.0), fake, NULL, NULL, NULL, C.c_void_p(0x100000),
+                        C.byref(have), NULL)
+    assert rc == _lib.TSNE_ERR_WORKSPACE
+
+
+def test_invalid_arguments_rejected(L):
+    fake = C.c_void_p(0x1000)
+    IA, UN = _lib.TSNE_ERR_INVALID_ARG, _lib.TSNE_ERR_UNSUPPORTED
+    # kNN
+    assert ws_query(L.tsne_knn, NULL, 100, 50, 10, 0, 0, fake, fake)[0] == IA
+    assert ws_query(L.tsne_knn, fake, 100, 50, 100, 0, 0, fake, fake)[0] == IA  # k >= n
+    assert ws_query(L.tsne_knn, fake, 1, 50, 1, 0, 0, fake, fake)[0] == IA  # n < 2
+    assert ws_query(L.tsne_knn, fake, 1000, 50, 300, 0, 0, fake, fake)[0] == UN  # k > 256
+    assert ws_query(L.tsne_knn, fake, 1000, 300, 10, 0, 0, fake, fake)[0] == UN  # d > 256
+    assert ws_query(L.tsne_knn, fake, 1000, 64, 10, 1, 20, fake, fake)[0] == UN  # bf16 needs d <= 58
+    assert ws_query(L.tsne_knn, fake, 1000, 50, 90, 1, 80, fake, fake)[0] == IA  # n_cand < k
+    assert ws_query(L.tsne_knn, fake, 1000, 50, 90, 7, 0, fake, fake)[0] == IA  # unknown precision
+    # calibration
+    cal = L.tsne_calibrate_P
+    assert cal(fake, 10, 30, C.c_float(30.0), C.c_float(1e-5), 200, fake, NULL, NULL, NULL, NULL) == IA  # perp >= k
+    assert cal(fake, 10, 30, C.c_float(10.0), C.c_float(0.0), 200, fake, NULL, NULL, NULL, NULL) == IA  # tol
+    assert cal(fake, 10, 30, C.c_float(10.0), C.c_float(1e-5), 0, fake, NULL, NULL, NULL, NULL) == IA  # max_iter
+    assert cal(NULL, 10, 30, C.c_float(10.0), C.c_float(1e-5), 9, fake, NULL, NULL, NULL, NULL) == IA
+    assert cal(fake, 10, 300, C.c_float(10.0), C.c_float(1e-5), 9, fake, NULL, NULL, NULL, NULL) == UN
+    # symmetrisation
+    assert ws_query(L.tsne_symmetrize, fake, fake, 100, 100, fake, fake, fake, fake, fake)[0] == IA
+    assert ws_query(L.tsne_symmetrize, fake, fake, 100, 10, fake, fake, fake, fake, NULL)[0] == IA  # nnz NULL
+    # gradient / step
+    assert ws_query(L.tsne_kl_grad, fake, 1, fake, fake, fake, C.c_float(1.0), fake, NULL, NULL, NULL)[0] == IA
+    assert ws_query(L.tsne_kl_grad, fake, 10, fake, fake, fake, C.c_float(0.0), fake, NULL, NULL, NULL)[0] == IA
+    assert ws_query(L.tsne_kl_grad, fake, 10, fake, fake, fake, C.c_float(1.0), NULL, NULL, NULL, NULL)[0] == IA
+    st = L.tsne_step
+    assert st(NULL, fake, fake, fake, 10, C.c_float(200), C.c_float(0.5), C.c_float(0.2), C.c_float(0.8),
+              C.c_float(0.01), NULL) == IA
+    assert st(fake, fake, fake, fake, 0, C.c_float(200), C.c_float(0.5), C.c_float(0.2), C.c_float(0.8),
+              C.c_float(0.01), NULL) == IA
+    # differentiation form
+    assert ws_query(L.tsne_kl_forward, 5, fake, 64, fake, fake, fake, fake, NULL)[0] == IA  # dtype
+    assert ws_query(L.tsne_kl_backward, 0, fake, 64, fake, fake, fake, NULL, fake, fake, NULL)[0] == IA  # tpos

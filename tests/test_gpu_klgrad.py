@@ -1,0 +1,99 @@
+"""GPU parity: tsne_kl_grad (gradient, Z, KL, per-row Z) against the FP64 oracle.
+
+Tolerance: norm-wise relative gradient error 1e-4 (the stated FP32 target),
+evaluated at the same float32 Y and P (widened exactly for the oracle).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import oracle_problem, random_graph_P, rel, say, sparse_to_dev, to_dev
+from paper_2605_13928_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+GRAD_RTOL = 1e-4
+
+
+def widen(S, v32):
+    return oracle.CSR(S.row_ptr, S.col, v32.astype(np.float64), S.tpos)
+
+
+def compare(dev, S, Y32, alpha, zrow=True):
+    v32 = S.val.astype(np.float32)
+    So = widen(S, v32)
+    P = sparse_to_dev(So, dev)
+    g, Z, kl, Zr = api.kl_grad(to_dev(Y32, dev), P, alpha, want_Z=True, want_kl=True, want_Zrow=zrow)
+    g = g.cpu().numpy().astype(np.float64)
+    go, Zo, klo = oracle.kl_grad(Y32.astype(np.float64), So, alpha)
+    e = rel(g, go)
+    assert e <= GRAD_RTOL, e
+    assert abs(Z.item() - Zo) <= 1e-6 * Zo
+    assert abs(kl.item() - klo) <= 1e-5 * max(1.0, abs(klo))
+    assert np.abs(g.sum(0)).max() <= 1e-5 * np.abs(g).sum()
+    if zrow:
+        Zro, _, _ = oracle.grad_rows(Y32.astype(np.float64), np.arange(Y32.shape[0]), None)
+        np.testing.assert_allclose(Zr.cpu().numpy(), Zro, rtol=1e-6)
+    return e
+
+
+@pytest.mark.parametrize("alpha", [12.0, 1.0])
+@pytest.mark.parametrize("ystd", [0.01, 1.0, 30.0])
+def test_klgrad_c1(dev, alpha, ystd):
+    say("klgrad c1", alpha, ystd)
+    X, labels, idx, d2, Pc, S = oracle_problem("c1", 1500, 90, 30.0)
+    Y = synth.random_embedding(1500, ystd, 77)
+    compare(dev, S, Y, alpha)
+
+
+@pytest.mark.parametrize("n", [2, 3, 97, 1024, 1025, 4097])
+def test_klgrad_ragged_sizes(dev, n):
+    say("klgrad ragged", n)
+    k = min(30, n - 1)
+    idx, d2, Pc, S = random_graph_P(n, k, min(10.0, k - 0.5), n)
+    Y = synth.random_embedding(n, 5.0, n + 1)
+    compare(dev, S, Y, 12.0)
+
+
+def test_klgrad_two_points_stationary(dev):
+    say("klgrad n=2")
+    S = oracle.CSR(np.array([0, 1, 2]), np.array([1, 0]), np.array([0.5, 0.5]))
+    Y = np.array([[0.3, -1.2], [2.0, 0.7]], np.float32)
+    P = sparse_to_dev(S, dev)
+    g, Z, kl, _ = api.kl_grad(to_dev(Y, dev), P, 1.0, want_Z=True, want_kl=True)
+    assert np.abs(g.cpu().numpy()).max() < 1e-6
+    assert abs(kl.item()) < 1e-6
+
+
+def test_klgrad_c2_full_size(dev):
+    # the benchmark's launch configuration: n = 20,000
+    say("klgrad c2 full")
+    n = 20_000
+    idx, d2, Pc, S = random_graph_P(n, 90, 30.0, 2)
+    for ystd, alpha in ((0.01, 12.0), (20.0, 1.0)):
+        Y = synth.random_embedding(n, ystd, 2000 + int(ystd))
+        compare(dev, S, Y, alpha, zrow=False)
+
+
+def test_klgrad_c5_sampled_rows(dev):
+    # full scale n = 1,000,000: per-row Z_i and gradient rows checked on a
+    # seeded sample of rows, plus sum_i Z_i = Z (a property at any size).
+    say("klgrad c5 sampled")
+    n = 1_000_000
+    idx, d2, Pc, S = random_graph_P(n, 90, 30.0, 5)
+    v32 = S.val.astype(np.float32)
+    So = widen(S, v32)
+    P = sparse_to_dev(So, dev)
+    Y = synth.random_embedding(n, 30.0, 2005)
+    g, Z, kl, Zr = api.kl_grad(to_dev(Y, dev), P, 1.0, want_Z=True, want_Zrow=True)
+    Zr = Zr.cpu().numpy()
+    Zg = Z.item()
+    assert abs(Zr.sum() - Zg) <= 1e-9 * Zg
+    rows = np.random.default_rng(5).choice(n, 192, replace=False)
+    Zo, Ro, Ao = oracle.grad_rows(Y.astype(np.float64), rows, So)
+    np.testing.assert_allclose(Zr[rows], Zo, rtol=1e-6)
+    # g_i = 4 (A_i - R_i / Z) with the oracle's A_i, R_i; Z from the checked row sums
+    go = 4.0 * (Ao - Ro / Zg)
+    e = rel(g.cpu().numpy()[rows], go)
+    assert e <= GRAD_RTOL, e
