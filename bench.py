@@ -1,0 +1,272 @@
+"""Benchmark of the exact t-SNE hot path on one MI355X.
+
+A step is one pass of the whole path over the workload's synthetic input,
+already resident in HBM: FP32 exact kNN, perplexity calibration,
+symmetrisation, then every gradient + optimiser iteration of the schedule.
+`value` = ordered pair interactions evaluated by tsne_kl_grad over the timed
+steps / wall time of those steps.  HIP events around each tsne_kl_grad call
+(on the stream it is launched on) give the dominant kernel's per-launch time
+for the roofline.  Outside the timed region: the BF16-MFMA vs FP32 kNN build
+comparison, and the CPU-baseline leg (the FP64 oracle timed on a bounded
+sample of the same workload, which also yields the error statistics).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+BF16_PEAK_TFLOPS = 2500.0  # dense
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--iters", type=int, default=None, help="override the schedule's iteration count")
+    ap.add_argument("--knn-compare-n", type=int, default=200_000,
+                    help="point count of the BF16-vs-FP32 kNN build comparison (C3 shape)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=30)
+    return ap.parse_args()
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KLGRAD_SOURCES = ["paper_2605_13928_amd/csrc/klgrad.hip", "paper_2605_13928_amd/csrc/rep.hpp"]
+
+
+def traffic_from_profile(digest):
+    """HBM bytes per tsne_kl_grad call from the committed PMC summary, if it
+    was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "kl_grad_c2_traffic.txt")
+    if not os.path.exists(p):
+        return None
+    vals = {}
+    for line in open(p):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != digest:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_call"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2605_13928_amd import api, synth, tsne
+
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS[args.workload]
+    iters = w.iters if args.iters is None else args.iters
+    n = w.n
+    X_np, labels = synth.make_points(w)
+    Y0_np = synth.make_init(w)
+    X = torch.from_numpy(X_np).to(dev)
+    Y0 = torch.from_numpy(Y0_np).to(dev)
+    ws = api.Workspace()
+    ws_grad = api.Workspace()
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step(events):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        idx, d2 = api.knn(X, w.k, w.knn, n_cand=(w.candidates if w.knn == "bf16" else None), ws=ws)
+        t1.record(stream)
+        Pc, beta, conv, nun = api.calibrate_P(d2, w.perplexity)
+        P = api.symmetrize(idx, Pc, want_tpos=False, ws=ws)
+        st = tsne.State.start(Y0)
+        for t in range(iters):
+            alpha, mom = tsne.schedule(w, t)
+            if events is not None:
+                a, b = events[t]
+                a.record(stream)
+            api.kl_grad(st.Y, P, alpha, grad=st.grad, ws=ws_grad)
+            if events is not None:
+                b.record(stream)
+            api.step(st.Y, st.update, st.gains, st.grad, w.lr, mom)
+        return (t0, t1), st, P, idx, d2, Pc
+
+    for _ in range(args.warmup):
+        one_step(None)
+    torch.cuda.synchronize()
+
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
+          for _ in range(args.steps)]
+    knn_ev = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        kev, st, P, idx, d2, Pc = one_step(ev[s])
+        knn_ev.append(kev)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+
+    pairs_per_step = float(n) * float(n - 1) * iters
+    value = pairs_per_step * args.steps / elapsed
+    grad_ms = np.array([a.elapsed_time(b) for s in range(args.steps) for (a, b) in ev[s]])
+    knn_fp32_s = float(np.median([a.elapsed_time(b) for a, b in knn_ev])) / 1e3
+    grad_ms_mean = float(grad_ms.mean())
+    flops_per_call = api.KLGRAD_FLOPS_PER_ORDERED_PAIR * float(n) * float(n - 1)
+    achieved_tflops = flops_per_call / (grad_ms_mean * 1e-3) / 1e12
+    digest = source_digest(KLGRAD_SOURCES)
+    traffic = traffic_from_profile(digest)
+
+    # --- BF16-MFMA vs FP32 kNN build, outside the timed region -------------
+    knn_cmp = {}
+    ncmp = args.knn_compare_n
+    if ncmp:
+        Xc_np, _ = synth.make_points("c3", n=ncmp)
+        Xc = torch.from_numpy(Xc_np).to(dev)
+        wsk = api.Workspace()
+
+        def time_knn(prec, reps):
+            out = None
+            ts = []
+            for r in range(reps + 1):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                out = api.knn(Xc, 90, prec, n_cand=(180 if prec == "bf16" else None), ws=wsk)
+                b.record(stream)
+                torch.cuda.synchronize()
+                if r > 0:
+                    ts.append(a.elapsed_time(b) / 1e3)
+            return float(np.median(ts)), out
+
+        t32, (i32, d32) = time_knn("fp32", 3)
+        t16, (i16, d16) = time_knn("bf16", 5)
+        a32 = i32.cpu().numpy()
+        a16 = i16.cpu().numpy()
+        same = np.mean([len(set(p) & set(q)) / 90 for p, q in zip(a16.tolist(), a32.tolist())])
+        mfma_flops = 2.0 * ncmp * ncmp * 64
+        knn_cmp = {"n": ncmp, "k": 90, "n_cand": 180, "fp32_exact_s": t32, "bf16_mfma_rerank_s": t16,
+                   "speedup": t32 / t16, "bf16_vs_fp32_set_agreement": float(same),
+                   "bf16_mfma_tflops_executed": mfma_flops / t16 / 1e12}
+        del Xc, i32, d32, i16, d16
+
+    # --- CPU baseline: the FP64 oracle on a bounded sample ------------------
+    cpu = None
+    errors = {}
+    # GPU-side error statistics that need no oracle: entropy at the returned
+    # beta recomputed in FP64 from the GPU's own distances, and sum P.
+    beta = api.calibrate_P(d2, w.perplexity)[1].cpu().numpy().astype(np.float64)
+    dd = d2.cpu().numpy().astype(np.float64)
+    s_ = dd - dd.min(1, keepdims=True)
+    e_ = np.exp(-beta[:, None] * s_)
+    H = np.log(e_.sum(1)) + beta * (e_ * s_).sum(1) / e_.sum(1)
+    errors["perplexity_H_max_abs_err_nats"] = float(np.abs(H - np.log(w.perplexity)).max())
+    errors["P_sum_abs_err"] = float(abs(P.val.double().sum().item() - 1.0))
+    if not args.no_cpu_baseline:
+        import oracle
+
+        thr = oracle.num_threads()
+        qrows = np.arange(0, n, 10, dtype=np.int64)
+        t0 = time.perf_counter()
+        oi, od = oracle.knn(X_np, w.k, rows=qrows)
+        t_knn = (time.perf_counter() - t0) * (n / qrows.size)
+        gi, gd = synth.random_knn_graph(n, w.k, w.data_seed)  # full-size seeded graph for the linear stages
+        t0 = time.perf_counter()
+        Pc_o, _, _, _ = oracle.calibrate(gd, w.perplexity, tol=1e-5)
+        S_o = oracle.symmetrize(gi, Pc_o)
+        t_ps = time.perf_counter() - t0
+        Sg = oracle.CSR(S_o.row_ptr, S_o.col, S_o.val.astype(np.float32).astype(np.float64))
+        Y = Y0_np.astype(np.float64)
+        U = np.zeros_like(Y)
+        G = np.ones_like(Y)
+        t0 = time.perf_counter()
+        for t in range(args.cpu_iters):
+            a, m = oracle.tsne_schedule(t, w.exaggeration, w.exaggeration_iters, w.momentum_early, w.momentum_late)
+            g, _, _ = oracle.kl_grad(Y, Sg, a, want_kl=False)
+            oracle.step(Y, U, G, g, w.lr, m)
+        t_it = (time.perf_counter() - t0) / args.cpu_iters
+        t_total = t_knn + t_ps + t_it * iters
+        cpu = {"value": pairs_per_step / t_total, "unit": "pair interactions/s", "cores": thr, "kind": "oracle",
+               "sample": (f"FP64 oracle, {thr} threads: exact kNN on {qrows.size} of {n} query rows (time x"
+                          f"{n // qrows.size}); calibration + symmetrisation of a full-size seeded k={w.k} graph; "
+                          f"{args.cpu_iters} of {iters} gradient+step iterations (time x{iters / args.cpu_iters:g}); "
+                          f"host {platform.processor() or platform.machine()}"),
+               "s_per_step_extrapolated": t_total}
+        # errors vs FP64 from identical inputs
+        g_idx = idx.cpu().numpy()[qrows]
+        errors["knn_set_agreement_sampled_rows"] = float(
+            np.mean([len(set(p) & set(q)) / w.k for p, q in zip(g_idx.tolist(), oi.tolist())]))
+        ddq = d2.cpu().numpy()[qrows].astype(np.float64)
+        same = g_idx == oi
+        errors["knn_d2_max_rel_on_agreeing_slots"] = float(
+            np.max(np.abs(ddq[same] - od[same]) / np.maximum(od[same], 1e-30)))
+        Pd = api.SparseP(torch.from_numpy(Sg.row_ptr).to(dev), torch.from_numpy(Sg.col).to(dev),
+                         torch.from_numpy(Sg.val.astype(np.float32)).to(dev), None, n)
+        for ystd, a in ((0.01, 12.0), (20.0, 1.0)):
+            Yt = synth.random_embedding(n, ystd, 99)
+            gg, Zg, klg, _ = api.kl_grad(torch.from_numpy(Yt).to(dev), Pd, a, want_Z=True, want_kl=True)
+            go, Zo, klo = oracle.kl_grad(Yt.astype(np.float64), Sg, a)
+            gg = gg.cpu().numpy().astype(np.float64)
+            errors[f"grad_rel_norm_ystd{ystd:g}"] = float(np.linalg.norm(gg - go) / np.linalg.norm(go))
+            errors[f"grad_max_entry_rel_ystd{ystd:g}"] = float(np.abs(gg - go).max() / np.abs(go).max())
+            errors[f"Z_rel_ystd{ystd:g}"] = abs(Zg.item() - Zo) / Zo
+            errors[f"KL_rel_ystd{ystd:g}"] = abs(klg.item() - klo) / abs(klo)
+
+    roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
+                "kernel": "tsne_kl_grad (all-pairs repulsion + CSR attraction/finalize)",
+                "flops_per_call": flops_per_call, "ms_per_call": grad_ms_mean,
+                "flops_per_ordered_pair": api.KLGRAD_FLOPS_PER_ORDERED_PAIR, "source_digest": digest}
+    rec = {
+        "metric": "KL-grad pair interactions/s + kNN build s, BF16-MFMA vs FP32 at stated error",
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: exact t-SNE, N={n} x {w.d}, {w.clusters}-cluster mixture "
+                               f"({w.weights} weights), perplexity {w.perplexity:g}, k={w.k}, {w.knn} kNN, "
+                               f"{iters} iterations",
+                   "n": n, "d": w.d, "k": w.k, "perplexity": w.perplexity, "iters": iters, "knn": w.knn},
+        "kl_grad_pairs_per_s": float(n) * (n - 1) / (grad_ms_mean * 1e-3),
+        "knn_build_s": {"fp32_exact_in_step": knn_fp32_s, **knn_cmp},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "errors_vs_fp64": errors,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()
