@@ -41,6 +41,8 @@ def parse():
                     help="point count of the BF16-vs-FP32 kNN build comparison (C3 shape)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="launch one device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -96,6 +98,13 @@ def main():
     ws = api.Workspace()
     ws_grad = api.Workspace()
     stream = torch.cuda.current_stream(dev)
+    if args.copy_calibration_mib:
+        # reads and writes exactly MiB * 2^20 bytes each (the MulFunctor elementwise kernel)
+        src = torch.ones(args.copy_calibration_mib * (1 << 18), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     def one_step(events):
         t0 = torch.cuda.Event(enable_timing=True)

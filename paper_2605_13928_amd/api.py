@@ -48,11 +48,14 @@ def _req(t, name, dtype, shape=None):
 
 
 class Workspace:
-    """Grow-only device scratch buffer reused across calls (one per owner)."""
+    """Grow-only device scratch buffer reused across calls, plus the sizes the
+    library asked for (keyed by entry point and shape) so repeated calls skip
+    the size query."""
 
     def __init__(self, device=None):
         self.device = device
         self.buf = None
+        self.sizes = {}
 
     def get(self, nbytes: int, device) -> torch.Tensor:
         if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
@@ -60,10 +63,16 @@ class Workspace:
         return self.buf
 
 
-def _run_with_workspace(name, fn, args_before, args_after, device, ws: Workspace | None):
-    need = C.c_size_t(0)
-    check(name, fn(*args_before, None, C.byref(need), *args_after))
-    buf = (ws or Workspace()).get(need.value, device)
+def _run_with_workspace(name, fn, args_before, args_after, device, ws: Workspace | None, key=None):
+    ws = ws or Workspace()
+    need = ws.sizes.get(key) if key is not None else None
+    if need is None:
+        q = C.c_size_t(0)
+        check(name, fn(*args_before, None, C.byref(q), *args_after))
+        need = q.value
+        if key is not None:
+            ws.sizes[key] = need
+    buf = ws.get(need, device)
     have = C.c_size_t(buf.numel())
     check(name, fn(*args_before, _ptr(buf), C.byref(have), *args_after))
     return buf
@@ -157,7 +166,7 @@ def kl_grad(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, grad: torch.
     L = _lib.load()
     _run_with_workspace("tsne_kl_grad", L.tsne_kl_grad,
                         (_ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val), float(exaggeration), _ptr(grad),
-                         _ptr(Z), _ptr(kl), _ptr(Zrow)), (_stream(dev),), dev, ws)
+                         _ptr(Z), _ptr(kl), _ptr(Zrow)), (_stream(dev),), dev, ws, key=("kl_grad", n, want_Zrow))
     return grad, Z, kl, Zrow
 
 

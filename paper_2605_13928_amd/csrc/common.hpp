@@ -130,6 +130,23 @@ __device__ __forceinline__ double block_sum_d(double v, double* lds /*256*/) {
   return r;
 }
 
+// Fixed-order sum of the per-block partials (Z), computed identically by
+// every block that needs it.
+__device__ __forceinline__ double sum_zblocks(const double* __restrict__ Zblock, int64_t nz, double* red) {
+  // eight independent loads in flight per thread, added in index order
+  double t = 0.0;
+  int64_t b = threadIdx.x;
+  for (; b + 7 * 256 < nz; b += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = Zblock[b + u * 256];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += v[u];
+  }
+  for (; b < nz; b += 256) t += Zblock[b];
+  return block_sum_d(t, red);
+}
+
 // ---------------------------------------------------------------------
 // Neighbour keys: (distance bits << 32) | index.  For distances >= 0 the
 // unsigned order of the bits is the numeric order, so the unsigned order of

@@ -1,64 +1,115 @@
 // tsne_kl_grad: exact t-SNE gradient with early exaggeration
 // (van der Maaten & Hinton 2008, eq. 5 and Sec. 3.4) and optional Z / KL.
-// Launch sequence: the all-pairs repulsion pass (rep.hpp), then one
-// finalize pass that gathers the sparse attraction over the CSR rows
-// (16 lanes per row, reduced with DPP row rotations), sums the repulsion
-// chunks and Z in a fixed order and writes g_i = 4 (alpha A_i - R_i / Z);
-// and, when KL is requested, a one-block reduction of the per-block
-// sum p ln p, sum p ln q (q = 1/w) and sum p.
+// Launch sequence: the symmetric all-pairs repulsion pass (rep_sym.hpp),
+// then a finalize pass that gathers the sparse attraction over the CSR rows,
+// sums the repulsion partials and Z in a fixed order and writes
+// g_i = 4 (alpha A_i - R_i / Z); and, when KL is requested, a one-block
+// reduction of the per-block sums p ln p, p ln q (q = 1/w) and p.
 #include "common.hpp"
-#include "rep.hpp"
+#include "rep_sym.hpp"
 
 namespace tsne {
 
+// Finalize, 16 rows per block.  Repulsion partials: lane group g adds
+// slices g, g + 16, ... of the block's rows in FP64, combined across groups
+// in a fixed order.  Attraction A_i = sum_{e in row i} p_e w_e (y_i - y_j):
+// 16 lanes per row, up to eight entries per lane in flight (all loads
+// issued before use), reduced by DPP row rotations; optional per-block sums
+// of p ln p, p ln q (q = 1/w) and p for the KL.  Then
+// g_i = 4 (alpha A_i - R_i / Z).
+constexpr int FIN_ROWS = 16;
+
 __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     const float2* __restrict__ Y, int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const float* __restrict__ val, float alpha, const double* __restrict__ Rpart, const double* __restrict__ Zrowpart,
-    int64_t S, const double* __restrict__ Zblock, int64_t nZ, float2* __restrict__ grad, double* __restrict__ Zrow,
+    const float* __restrict__ val, float alpha, const float2* __restrict__ Rpart, const float* __restrict__ Zrowpart,
+    int64_t ns, const double* __restrict__ Zblock, int64_t nZ, float2* __restrict__ grad, double* __restrict__ Zrow,
     double* __restrict__ Z_out, double* __restrict__ klpart) {
   __shared__ double red[256];
+  __shared__ double pr[16][FIN_ROWS][3];
+  __shared__ float2 att[FIN_ROWS];
   const int tid = threadIdx.x;
-  const double Z = sum_zblocks(Zblock, nZ, red);
-  if (blockIdx.x == 0 && tid == 0 && Z_out) *Z_out = Z;
+  const int g = tid >> 4, sl = tid & 15;
+  const int64_t r0 = int64_t(blockIdx.x) * FIN_ROWS;
 
-  const int64_t row = int64_t(blockIdx.x) * 16 + (tid >> 4);
-  const int sl = tid & 15;
+  // attraction: lane group g owns row r0 + g (loads first, so they overlap
+  // with the partial sums below)
+  const int64_t row = r0 + g;
   float ax = 0.0f, ay = 0.0f, plp = 0.0f, plq = 0.0f, ps = 0.0f;
   if (row < n) {
     const float2 yi = Y[row];
     const int64_t e1 = row_ptr[row + 1];
-    for (int64_t e = row_ptr[row] + sl; e < e1; e += 16) {
-      const int32_t j = col[e];
-      const float p = val[e];
-      const float2 yj = Y[j];
-      const float dx = yi.x - yj.x, dy = yi.y - yj.y;
-      const float q = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f));
-      const float pw = p * __builtin_amdgcn_rcpf(q);
-      ax = __builtin_fmaf(pw, dx, ax);
-      ay = __builtin_fmaf(pw, dy, ay);
-      if (klpart) {
-        if (p > 0.0f) plp += p * logf(p);
-        plq += p * logf(q);
-        ps += p;
+    for (int64_t e = row_ptr[row] + sl; e < e1; e += 128) {
+      int32_t jj[8];
+      float pp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t ee = e + 16 * u;
+        const bool ok = ee < e1;
+        jj[u] = ok ? col[ee] : int32_t(row);
+        pp[u] = ok ? val[ee] : 0.0f;
+      }
+      float2 yj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) yj[u] = Y[jj[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float dx = yi.x - yj[u].x, dy = yi.y - yj[u].y;
+        const float q = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f));
+        const float pw = pp[u] * __builtin_amdgcn_rcpf(q);
+        ax = __builtin_fmaf(pw, dx, ax);
+        ay = __builtin_fmaf(pw, dy, ay);
+        if (klpart) {
+          if (pp[u] > 0.0f) plp += pp[u] * logf(pp[u]);
+          plq += pp[u] * logf(q);
+          ps += pp[u];
+        }
       }
     }
   }
+  {  // repulsion partials: thread (g, sl) takes row r0 + sl, slices g, g+16, ...
+    const int64_t prow = r0 + sl;
+    double rx = 0.0, ry = 0.0, zr = 0.0;
+    if (prow < n) {
+      int64_t k = g;
+      for (; k + 48 < ns; k += 64) {
+        float2 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = Rpart[(k + 16 * u) * n + prow];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          rx += double(r[u].x);
+          ry += double(r[u].y);
+        }
+      }
+      for (; k < ns; k += 16) {
+        const float2 r = Rpart[k * n + prow];
+        rx += double(r.x);
+        ry += double(r.y);
+      }
+      if (Zrow)
+        for (int64_t kk = g; kk < ns; kk += 16) zr += double(Zrowpart[kk * n + prow]);
+    }
+    pr[g][sl][0] = rx;
+    pr[g][sl][1] = ry;
+    pr[g][sl][2] = zr;
+  }
   ax = row16_sum(ax);
   ay = row16_sum(ay);
-  if (row < n && sl == 0) {
-    double rx = 0.0, ry = 0.0;
-    for (int64_t s = 0; s < S; ++s) {
-      rx += Rpart[2 * (s * n + row)];
-      ry += Rpart[2 * (s * n + row) + 1];
+  if (sl == 0) att[g] = make_float2(ax, ay);
+  const double Z = sum_zblocks(Zblock, nZ, red);  // its barriers also publish pr and att
+  if (blockIdx.x == 0 && tid == 0 && Z_out) *Z_out = Z;
+  if (tid < FIN_ROWS && r0 + tid < n) {
+    double Rx = 0.0, Ry = 0.0, Zr = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      Rx += pr[k][tid][0];
+      Ry += pr[k][tid][1];
+      Zr += pr[k][tid][2];
     }
-    const double gx = 4.0 * (double(alpha) * double(ax) - rx / Z);
-    const double gy = 4.0 * (double(alpha) * double(ay) - ry / Z);
-    grad[row] = make_float2(float(gx), float(gy));
-    if (Zrow) {
-      double zr = 0.0;
-      for (int64_t s = 0; s < S; ++s) zr += Zrowpart[s * n + row];
-      Zrow[row] = zr;
-    }
+    const float2 a = att[tid];
+    grad[r0 + tid] = make_float2(float(4.0 * (double(alpha) * double(a.x) - Rx / Z)),
+                                 float(4.0 * (double(alpha) * double(a.y) - Ry / Z)));
+    if (Zrow) Zrow[r0 + tid] = Zr;
   }
   if (klpart) {
     plp = row16_sum(plp);
@@ -103,31 +154,37 @@ extern "C" int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, c
   if (!Y || !row_ptr || !col || !val || !grad || n < 2) return TSNE_ERR_INVALID_ARG;
   if (!(exaggeration > 0.0f) || !(exaggeration < INFINITY)) return TSNE_ERR_INVALID_ARG;
   if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
-  const RepGrid g = RepGrid::make(n, REP_IREG);
-  const int64_t nfin = ceil_div(n, 16);
+  const SymGrid g = SymGrid::make(n);
+  const int64_t nfin = ceil_div(n, FIN_ROWS);
   Carve c;
-  const size_t o_R = c.take(sizeof(double) * 2 * size_t(g.S) * size_t(n));
-  const size_t o_Zr = c.take(sizeof(double) * size_t(g.S) * size_t(n));
-  const size_t o_Zb = c.take(sizeof(double) * size_t(g.blocks()));
+  const size_t o_R = c.take(sizeof(float2) * size_t(g.ns) * size_t(n));
+  const size_t o_Zr = c.take(sizeof(float) * size_t(g.ns) * size_t(n));
+  const size_t o_Zb = c.take(sizeof(double) * size_t(g.nwg));
   const size_t o_kl = c.take(sizeof(double) * 3 * size_t(nfin));
   int rc = workspace_protocol(workspace, workspace_bytes, c.off);
   if (rc >= 0) return rc;
   char* ws = static_cast<char*>(workspace);
-  double* Rpart = reinterpret_cast<double*>(ws + o_R);
-  double* Zrowpart = Zrow ? reinterpret_cast<double*>(ws + o_Zr) : nullptr;
+  float* Rpart = reinterpret_cast<float*>(ws + o_R);
+  float* Zrowpart = Zrow ? reinterpret_cast<float*>(ws + o_Zr) : nullptr;
   double* Zblock = reinterpret_cast<double*>(ws + o_Zb);
   double* klpart = kl ? reinterpret_cast<double*>(ws + o_kl) : nullptr;
   hipStream_t s = as_stream(stream);
+  const float2* Y2 = reinterpret_cast<const float2*>(Y);
 
-  hipLaunchKernelGGL((rep_kernel<float, REP_IREG, true>), dim3(unsigned(g.nib), unsigned(g.S)), dim3(256), 0, s, Y, n,
-                     g.jchunk, Rpart, Zrowpart, Zblock);
+  const size_t lds = rep_sym_lds_bytes(g.S, Zrow != nullptr);
+  if (Zrow)
+    hipLaunchKernelGGL(rep_sym_kernel<true>, dim3(unsigned(g.nwg)), dim3(256), lds, s, Y2, n, int(g.S), g.ns, Rpart,
+                       Zrowpart, Zblock);
+  else
+    hipLaunchKernelGGL(rep_sym_kernel<false>, dim3(unsigned(g.nwg)), dim3(256), lds, s, Y2, n, int(g.S), g.ns, Rpart,
+                       Zrowpart, Zblock);
   TSNE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(finalize_tsne_kernel, dim3(unsigned(nfin)), dim3(256), 0, s, reinterpret_cast<const float2*>(Y), n,
-                     row_ptr, col, val, exaggeration, Rpart, Zrowpart, g.S, Zblock, g.blocks(),
+  hipLaunchKernelGGL(finalize_tsne_kernel, dim3(unsigned(nfin)), dim3(256), 0, s, Y2, n, row_ptr, col, val, exaggeration,
+                     reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, Zblock, g.nwg,
                      reinterpret_cast<float2*>(grad), Zrow, Z, klpart);
   TSNE_CHECK_LAUNCH();
   if (kl) {
-    hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, klpart, nfin, Zblock, g.blocks(), kl);
+    hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, klpart, nfin, Zblock, g.nwg, kl);
     TSNE_CHECK_LAUNCH();
   }
   return TSNE_OK;

@@ -21,10 +21,15 @@ namespace tsne {
 // ---------------------------------------------------------------------
 // Candidate buffers.
 
+// A row's buffer is only ever written and read by the wave that owns the
+// row, so workgroup scope suffices: wait for this wave's stores, no cache
+// write-back or invalidation beyond the CU.
+__device__ __forceinline__ void wg_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
 template <int EPL>
 __device__ void compact_row(uint64_t* __restrict__ buf, int* cnt, float* tau, int keep) {
   const int lane = lane_id();
-  __threadfence();  // earlier appends of this wave visible to the loads below
+  wg_fence();  // earlier appends of this wave visible to the loads below
   const int c = *cnt;
   uint64_t v[EPL];
 #pragma unroll
@@ -40,7 +45,7 @@ __device__ void compact_row(uint64_t* __restrict__ buf, int* cnt, float* tau, in
   }
   float nt = INFINITY;
   if (c >= keep) nt = key_dist(wave_pick<EPL>(v, keep - 1));
-  __threadfence();
+  wg_fence();
   if (lane == 0) {
     *cnt = c < keep ? c : keep;
     *tau = nt;
@@ -52,7 +57,7 @@ template <int EPL>
 __device__ void emit_row(const uint64_t* __restrict__ buf, int c, int keep, int32_t* __restrict__ oidx,
                          float* __restrict__ od2) {
   const int lane = lane_id();
-  __threadfence();
+  wg_fence();
   uint64_t v[EPL];
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {

@@ -152,12 +152,4 @@ struct RepGrid {
   int64_t blocks() const { return nib * S; }
 };
 
-// Fixed-order sum of the per-block Z partials, computed identically by
-// every block that needs it.
-__device__ __forceinline__ double sum_zblocks(const double* __restrict__ Zblock, int64_t nz, double* red) {
-  double t = 0.0;
-  for (int64_t b = threadIdx.x; b < nz; b += 256) t += Zblock[b];
-  return block_sum_d(t, red);
-}
-
 }  // namespace tsne

@@ -1,0 +1,336 @@
+// Symmetric all-pairs repulsion (FP32): every unordered pair {i, j} is
+// evaluated once and its Student-t weight w = 1 / (1 + ||y_i - y_j||^2)
+// (van der Maaten & Hinton 2008, eq. 4) feeds both rows:
+//   R_i += w^2 (y_i - y_j),  R_j -= w^2 (y_i - y_j),  Z += 2 w.
+// That halves the reciprocals and differences of the ordered-pair sweep.
+//
+// Decomposition.  Points are cut into superblocks of S (a multiple of 64);
+// a workgroup of 4 waves owns one superblock pair (s, t), s <= t.  A wave
+// tile is 64 i-points x 64 j-points on an 8 x 8 lane grid: lane (a, b)
+// = lane (8a + b) holds i-points 8a..8a+7 and j-points 8b..8b+7 in
+// registers and evaluates their 64 pairs with no data movement.  Each wave
+// sweeps its i-subblocks (64 points of s, round robin over the 4 waves)
+// across the j-tiles of t (staged in LDS): i-side sums stay in registers;
+// after every tile the j-side sums are reduce-scattered over the 8 lanes
+// that share a j-group (gfx950 v_permlane32_swap / v_permlane16_swap, then
+// a DPP row rotation) and added to the wave's own LDS accumulator.  At the
+// end the workgroup adds the 4 wave accumulators in a fixed order and
+// writes one partial per point and opposite superblock: part[t][i] for
+// i in s and part[s][j] for j in t (for s == t both sides land in the same
+// slot and are added first).  A later pass sums the ns partials of a row in
+// index order, so the result is deterministic.
+// In the diagonal superblock, tiles below the diagonal are skipped and the
+// 64 x 64 diagonal tiles take every ordered pair on the i side only, with
+// the self pair masked.  Points past n are placed far away,
+// each at its own position, so all their weights are exactly 0.
+#pragma once
+
+#include "common.hpp"
+
+namespace tsne {
+
+constexpr int SYM_WAVES = 4;
+
+// --- exchange steps of the 8-lane reduce-scatter -------------------------
+// Each step halves the values a lane holds: for pairs (x, y) = (v[k], v[k+h])
+// the lanes with the step's bit clear end with x summed over the lane pair,
+// the others with y summed.
+
+// lanes l and l ^ 32 (v_permlane32_swap: the upper half of x trades places
+// with the lower half of y)
+__device__ __forceinline__ float xstep32(float x, float y) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// lanes l and l ^ 16 (v_permlane16_swap: odd 16-lane rows of x trade places
+// with even rows of y)
+__device__ __forceinline__ float xstep16(float x, float y) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// lanes l and l ^ 8 (DPP row rotation by 8 within rows of 16)
+__device__ __forceinline__ float xstep8(float x, float y, bool hi) {
+  const float send = hi ? x : y;
+  const float keep = hi ? y : x;
+  return keep + dpp_f<0x128>(send);
+}
+// lanes l and l ^ m, m in {1, 2, 4} (ds_swizzle bit-mask mode: xor m)
+template <int M>
+__device__ __forceinline__ float xstep_small(float x, float y, bool hi) {
+  const float send = hi ? x : y;
+  const float keep = hi ? y : x;
+  const float recv = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(send), 0x1F | (M << 10)));
+  return keep + recv;
+}
+
+// Reduce-scatter of v[0..15] over the 8 lanes sharing (lane & 7): after it,
+// the lane holds v[base] and v[base + 1] summed over those lanes, with
+// base = 8*bit5 + 4*bit4 + 2*bit3.
+__device__ __forceinline__ void rs16_hi(const float (&v)[16], float& o0, float& o1) {
+  const int lane = lane_id();
+  float u[8], t[4];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) u[k] = xstep32(v[k], v[k + 8]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t[k] = xstep16(u[k], u[k + 4]);
+  const bool h3 = (lane >> 3) & 1;
+  o0 = xstep8(t[0], t[2], h3);
+  o1 = xstep8(t[1], t[3], h3);
+}
+// Same for 8 values: the lane ends with v[4*bit5 + 2*bit4 + bit3].
+__device__ __forceinline__ float rs8_hi(const float (&v)[8]) {
+  const int lane = lane_id();
+  float u[4], t[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = xstep32(v[k], v[k + 4]);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) t[k] = xstep16(u[k], u[k + 2]);
+  return xstep8(t[0], t[1], (lane >> 3) & 1);
+}
+// Reduce-scatter over the 8 lanes sharing (lane >> 3): the lane holds
+// v[base], v[base + 1] with base = 8*bit2 + 4*bit1 + 2*bit0.
+__device__ __forceinline__ void rs16_lo(const float (&v)[16], float& o0, float& o1) {
+  const int lane = lane_id();
+  float u[8], t[4];
+  const bool b2 = (lane >> 2) & 1, b1 = (lane >> 1) & 1, b0 = lane & 1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) u[k] = xstep_small<4>(v[k], v[k + 8], b2);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t[k] = xstep_small<2>(u[k], u[k + 4], b1);
+  o0 = xstep_small<1>(t[0], t[2], b0);
+  o1 = xstep_small<1>(t[1], t[3], b0);
+}
+__device__ __forceinline__ float rs8_lo(const float (&v)[8]) {
+  const int lane = lane_id();
+  float u[4], t[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = xstep_small<4>(v[k], v[k + 4], (lane >> 2) & 1);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) t[k] = xstep_small<2>(u[k], u[k + 2], (lane >> 1) & 1);
+  return xstep_small<1>(t[0], t[1], lane & 1);
+}
+
+// Position of point p: its coordinates, or for p >= n a far point of its
+// own (pairs among such points have dy^2 = inf, so w = 0 as well).
+__device__ __forceinline__ float2 load_point(const float2* __restrict__ Y, int64_t p, int64_t n) {
+  if (p < n) return Y[p];
+  return make_float2(1e30f, 1e25f * float(p - n + 1));
+}
+
+#ifndef TSNE_SYM_MIN_WG
+#define TSNE_SYM_MIN_WG 1024
+#endif
+
+struct SymGrid {
+  int64_t S, ns, nwg;
+  static SymGrid make(int64_t n) {
+    SymGrid g;
+    // largest S in {1024, 512, 256, 128, 64} that still gives enough workgroups
+    int64_t S = 1024;
+    while (S > 64) {
+      const int64_t ns = ceil_div(n, S);
+      if (ns * (ns + 1) / 2 >= TSNE_SYM_MIN_WG) break;
+      S >>= 1;
+    }
+    g.S = S;
+    g.ns = ceil_div(n, S);
+    g.nwg = g.ns * (g.ns + 1) / 2;
+    return g;
+  }
+};
+
+// Workgroup id -> (s, t), s <= t, row-major over t.
+__device__ __forceinline__ void wg_pair(int64_t g, int64_t& s, int64_t& t) {
+  int64_t tt = int64_t((sqrt(8.0 * double(g) + 1.0) - 1.0) * 0.5);
+  while ((tt + 1) * (tt + 2) / 2 <= g) ++tt;
+  while (tt * (tt + 1) / 2 > g) --tt;
+  t = tt;
+  s = g - tt * (tt + 1) / 2;
+}
+
+// One 64 x 64 wave tile.  DIAG: i and j blocks coincide; all ordered pairs
+// go to the i side, self pairs masked, Z weight 1 (else 2, via the caller).
+template <bool DIAG, bool ZROW>
+__device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)[8], const float2* __restrict__ pj,
+                                         float (&rix)[8], float (&riy)[8], float (&zi)[8], float (&rj)[16],
+                                         float (&zj)[8], float& z, bool same_group) {
+  float xj[8], yj[8];
+#pragma unroll
+  for (int c = 0; c < 8; c += 2) {
+    const float4 v = *reinterpret_cast<const float4*>(pj + c);
+    xj[c] = v.x;
+    yj[c] = v.y;
+    xj[c + 1] = v.z;
+    yj[c + 1] = v.w;
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    rj[c] = 0.0f;
+    rj[8 + c] = 0.0f;
+    if (ZROW) zj[c] = 0.0f;
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float dx = xi[r] - xj[c], dy = yi[r] - yj[c];
+      const float q = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f));
+      float w = __builtin_amdgcn_rcpf(q);
+      if (DIAG && r == c) w = same_group ? 0.0f : w;
+      z += w;
+      const float w2 = w * w;
+      rix[r] = __builtin_fmaf(w2, dx, rix[r]);
+      riy[r] = __builtin_fmaf(w2, dy, riy[r]);
+      if (ZROW) zi[r] += w;
+      if (!DIAG) {
+        rj[c] = __builtin_fmaf(w2, dx, rj[c]);
+        rj[8 + c] = __builtin_fmaf(w2, dy, rj[8 + c]);
+        if (ZROW) zj[c] += w;
+      }
+    }
+  }
+}
+
+// LDS layout of a workgroup (floats): pts[2*S] | iacc[NC*S] | jacc[4][NC*S]
+// with NC = 2 (x, y) or 3 (x, y, Z_row), component-major per accumulator.
+template <bool ZROW>
+__global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__ Y, int64_t n, int S, int64_t ns,
+                                                      float* __restrict__ part, float* __restrict__ zpart,
+                                                      double* __restrict__ Zblock) {
+  constexpr int NC = ZROW ? 3 : 2;
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  __shared__ double red[256];
+  float2* pts = reinterpret_cast<float2*>(lds);
+  float* iacc = lds + 2 * S;
+  float* jacc = iacc + NC * S;
+  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int a = lane >> 3, b = lane & 7;
+  int64_t s, t;
+  wg_pair(blockIdx.x, s, t);
+  const bool diag_sb = s == t;
+  const int64_t i0 = s * S, j0 = t * S;
+  const int nsub = S / 64;
+
+  for (int u = tid; u < S; u += 256) pts[u] = load_point(Y, j0 + u, n);
+  for (int u = tid; u < NC * S; u += 256) iacc[u] = 0.0f;
+  for (int u = tid; u < SYM_WAVES * NC * S; u += 256) jacc[u] = 0.0f;
+  __syncthreads();
+
+  float* myj = jacc + w * NC * S;
+  double zsum = 0.0;
+  for (int us = w; us < nsub; us += SYM_WAVES) {
+    // this wave's i-subblock: points i0 + 64 us + 8a + r
+    float xi[8], yi[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const float2 p = load_point(Y, i0 + 64 * us + 8 * a + r, n);
+      xi[r] = p.x;
+      yi[r] = p.y;
+    }
+    float rix[8], riy[8], zi[8];
+    // after each fold this lane owns component bit2 of points 8a + c0 and
+    // 8a + c0 + 1 (c0 = 4 bit1 + 2 bit0), and Z_row of point 8a + cz
+    double di[2] = {0.0, 0.0}, dz = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) rix[r] = riy[r] = zi[r] = 0.0f;
+    const int v0 = diag_sb ? us : 0;
+    int since_fold = 0;
+    for (int v = v0; v < nsub; ++v) {
+      float rj[16], zj[8];
+      float z = 0.0f;
+      const float2* pj = pts + 64 * v + 8 * b;
+      if (diag_sb && v == us) {
+        sym_tile<true, ZROW>(xi, yi, pj, rix, riy, zi, rj, zj, z, a == b);
+        zsum += double(z);
+      } else {
+        sym_tile<false, ZROW>(xi, yi, pj, rix, riy, zi, rj, zj, z, false);
+        zsum += 2.0 * double(z);
+        // j side: reduce over the 8 lanes of this j-group, add into LDS
+        float o0, o1;
+        rs16_hi(rj, o0, o1);
+        const int comp = lane >> 5;
+        const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
+        float2* dst = reinterpret_cast<float2*>(myj + comp * S + 64 * v + 8 * b + c0);
+        float2 cur = *dst;
+        cur.x += o0;
+        cur.y += o1;
+        *dst = cur;
+        if (ZROW) {
+          const float oz = rs8_hi(zj);
+          const int cz = 4 * ((lane >> 5) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 3) & 1);
+          myj[2 * S + 64 * v + 8 * b + cz] += oz;
+        }
+      }
+      // fold the i-side sums into FP64 every 8 tiles (after an 8-lane reduce)
+      if (++since_fold == 8 || v == nsub - 1) {
+        since_fold = 0;
+        float vi[16];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          vi[r] = rix[r];
+          vi[8 + r] = riy[r];
+          rix[r] = riy[r] = 0.0f;
+        }
+        float o0, o1;
+        rs16_lo(vi, o0, o1);
+        di[0] += double(o0);
+        di[1] += double(o1);
+        if (ZROW) {
+          const float oz = rs8_lo(zi);
+          dz += double(oz);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) zi[r] = 0.0f;
+        }
+      }
+    }
+    // i side of this subblock -> LDS (each point owned by exactly one wave)
+    {
+      const int comp = (lane >> 2) & 1;
+      const int c0 = 2 * (lane & 1) + 4 * ((lane >> 1) & 1);
+      float* dst = iacc + comp * S + 64 * us + 8 * a + c0;
+      dst[0] = float(di[0]);
+      dst[1] = float(di[1]);
+      if (ZROW) {
+        const int cz = 4 * ((lane >> 2) & 1) + 2 * ((lane >> 1) & 1) + (lane & 1);
+        iacc[2 * S + 64 * us + 8 * a + cz] = float(dz);
+      }
+    }
+  }
+  __syncthreads();
+
+  // write the partials: part[t][i in s] and part[s][j in t]
+  for (int u = tid; u < S; u += 256) {
+    float jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+    for (int ww = 0; ww < SYM_WAVES; ++ww) {
+      jx += jacc[ww * NC * S + u];
+      jy += jacc[ww * NC * S + S + u];
+      if (ZROW) jz += jacc[ww * NC * S + 2 * S + u];
+    }
+    const int64_t pi = i0 + u, pj = j0 + u;
+    if (diag_sb) {
+      if (pi < n) {
+        reinterpret_cast<float2*>(part)[t * n + pi] = make_float2(iacc[u] - jx, iacc[S + u] - jy);
+        if (ZROW) zpart[t * n + pi] = iacc[2 * S + u] + jz;
+      }
+    } else {
+      if (pi < n) {
+        reinterpret_cast<float2*>(part)[t * n + pi] = make_float2(iacc[u], iacc[S + u]);
+        if (ZROW) zpart[t * n + pi] = iacc[2 * S + u];
+      }
+      if (pj < n) {
+        reinterpret_cast<float2*>(part)[s * n + pj] = make_float2(-jx, -jy);
+        if (ZROW) zpart[s * n + pj] = jz;
+      }
+    }
+  }
+  const double bz = block_sum_d(zsum, red);
+  if (tid == 0) Zblock[blockIdx.x] = bz;
+}
+
+inline size_t rep_sym_lds_bytes(int64_t S, bool zrow) {
+  const int nc = zrow ? 3 : 2;
+  return sizeof(float) * size_t(S) * size_t(2 + nc + SYM_WAVES * nc);
+}
+
+}  // namespace tsne
