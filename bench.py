@@ -3,10 +3,11 @@
 A step is one pass of the whole path over the workload's synthetic input,
 already resident in HBM: FP32 exact kNN, perplexity calibration,
 symmetrisation, then every gradient + optimiser iteration of the schedule.
-`value` = ordered pair interactions evaluated by tsne_kl_grad over the timed
-steps / wall time of those steps.  HIP events around each tsne_kl_grad call
-(on the stream it is launched on) give the dominant kernel's per-launch time
-for the roofline.  Outside the timed region: the BF16-MFMA vs FP32 kNN build
+`value` = ordered pair interactions evaluated by the gradient over the timed
+steps / wall time of those steps.  The iterations run through tsne_optimize,
+which records HIP events (on the stream the kernels are launched on) right
+around each gradient evaluation: they give the dominant kernel's per-launch
+time for the roofline.  Outside the timed region: the BF16-MFMA vs FP32 kNN build
 comparison, and the CPU-baseline leg (the FP64 oracle timed on a bounded
 sample of the same workload, which also yields the error statistics).
 
@@ -54,7 +55,8 @@ def source_digest(paths):
     return h.hexdigest()[:16]
 
 
-KLGRAD_SOURCES = ["paper_2605_13928_amd/csrc/klgrad.hip", "paper_2605_13928_amd/csrc/rep.hpp"]
+KLGRAD_SOURCES = ["paper_2605_13928_amd/csrc/klgrad.hip", "paper_2605_13928_amd/csrc/klgrad.hpp",
+                  "paper_2605_13928_amd/csrc/rep_sym.hpp", "paper_2605_13928_amd/csrc/common.hpp"]
 
 
 def traffic_from_profile(digest):
@@ -106,6 +108,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    ws_opt = api.Workspace()
+
     def one_step(events):
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
@@ -115,23 +119,19 @@ def main():
         Pc, beta, conv, nun = api.calibrate_P(d2, w.perplexity)
         P = api.symmetrize(idx, Pc, want_tpos=False, ws=ws)
         st = tsne.State.start(Y0)
-        for t in range(iters):
-            alpha, mom = tsne.schedule(w, t)
-            if events is not None:
-                a, b = events[t]
-                a.record(stream)
-            api.kl_grad(st.Y, P, alpha, grad=st.grad, ws=ws_grad)
-            if events is not None:
-                b.record(stream)
-            api.step(st.Y, st.update, st.gains, st.grad, w.lr, mom)
+        api.optimize(st.Y, st.update, st.gains, P, 0, iters, w.lr, w.exaggeration, w.exaggeration_iters,
+                     w.momentum_early, w.momentum_late, events=events, ws=ws_opt)
         return (t0, t1), st, P, idx, d2, Pc
 
     for _ in range(args.warmup):
         one_step(None)
     torch.cuda.synchronize()
 
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
-          for _ in range(args.steps)]
+    # two events per iteration per timed step, created (recorded once) up front
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * iters)] for _ in range(args.steps)]
+    for evs in ev:
+        for e in evs:
+            e.record(stream)
     knn_ev = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -143,7 +143,7 @@ def main():
 
     pairs_per_step = float(n) * float(n - 1) * iters
     value = pairs_per_step * args.steps / elapsed
-    grad_ms = np.array([a.elapsed_time(b) for s in range(args.steps) for (a, b) in ev[s]])
+    grad_ms = np.array([ev[s][2 * i].elapsed_time(ev[s][2 * i + 1]) for s in range(args.steps) for i in range(iters)])
     knn_fp32_s = float(np.median([a.elapsed_time(b) for a, b in knn_ev])) / 1e3
     grad_ms_mean = float(grad_ms.mean())
     flops_per_call = api.KLGRAD_FLOPS_PER_ORDERED_PAIR * float(n) * float(n - 1)
@@ -178,11 +178,31 @@ def main():
         a32 = i32.cpu().numpy()
         a16 = i16.cpu().numpy()
         same = np.mean([len(set(p) & set(q)) / 90 for p, q in zip(a16.tolist(), a32.tolist())])
+        # P built from each neighbour graph (same calibration and symmetrisation kernels)
+        import scipy.sparse as sp
+
+        def p_of(i, d):
+            S = api.symmetrize(i, api.calibrate_P(d, 30.0)[0], want_tpos=False, ws=wsk)
+            return sp.csr_matrix((S.val.cpu().numpy().astype(np.float64), S.col.cpu().numpy(),
+                                  S.row_ptr.cpu().numpy()), shape=(ncmp, ncmp))
+
+        P32, P16 = p_of(i32, d32), p_of(i16, d16)
+        diff = abs(P16 - P32)
+        both = P32.multiply(P16 != 0).tocsr()
+        rel = abs(both - P16.multiply(P32 != 0)).multiply(both.power(-1)).tocsr() if both.nnz else both
+        rows_same = np.flatnonzero((np.sort(a16, 1) == np.sort(a32, 1)).all(1))
+        dsl = d32.cpu().numpy()[rows_same].astype(np.float64)
+        d16s = d16.cpu().numpy()[rows_same].astype(np.float64)
         mfma_flops = 2.0 * ncmp * ncmp * 64
         knn_cmp = {"n": ncmp, "k": 90, "n_cand": 180, "fp32_exact_s": t32, "bf16_mfma_rerank_s": t16,
                    "speedup": t32 / t16, "bf16_vs_fp32_set_agreement": float(same),
+                   "bf16_vs_fp32_rows_identical": float(rows_same.size / ncmp),
+                   "bf16_vs_fp32_d2_max_rel_identical_rows": float(
+                       np.max(np.abs(d16s - dsl) / np.maximum(dsl, 1e-30))) if rows_same.size else None,
+                   "bf16_vs_fp32_P_L1": float(diff.sum()),
+                   "bf16_vs_fp32_P_max_rel_common": float(rel.max()) if rel.nnz else 0.0,
                    "bf16_mfma_tflops_executed": mfma_flops / t16 / 1e12}
-        del Xc, i32, d32, i16, d16
+        del Xc, i32, d32, i16, d16, P32, P16, diff, both, rel
 
     # --- CPU baseline: the FP64 oracle on a bounded sample ------------------
     cpu = None
@@ -200,7 +220,9 @@ def main():
         import oracle
 
         thr = oracle.num_threads()
-        qrows = np.arange(0, n, 10, dtype=np.int64)
+        big = n > 100_000
+        qrows = (np.random.default_rng(7).choice(n, 200, replace=False).astype(np.int64) if big
+                 else np.arange(0, n, 10, dtype=np.int64))
         t0 = time.perf_counter()
         oi, od = oracle.knn(X_np, w.k, rows=qrows)
         t_knn = (time.perf_counter() - t0) * (n / qrows.size)
@@ -211,20 +233,30 @@ def main():
         t_ps = time.perf_counter() - t0
         Sg = oracle.CSR(S_o.row_ptr, S_o.col, S_o.val.astype(np.float32).astype(np.float64))
         Y = Y0_np.astype(np.float64)
-        U = np.zeros_like(Y)
-        G = np.ones_like(Y)
-        t0 = time.perf_counter()
-        for t in range(args.cpu_iters):
-            a, m = oracle.tsne_schedule(t, w.exaggeration, w.exaggeration_iters, w.momentum_early, w.momentum_late)
-            g, _, _ = oracle.kl_grad(Y, Sg, a, want_kl=False)
-            oracle.step(Y, U, G, g, w.lr, m)
-        t_it = (time.perf_counter() - t0) / args.cpu_iters
+        if big:
+            # the full FP64 gradient is O(n^2) per iteration: time per-row parts
+            # (Z_i, repulsion, attraction; O(n) each) on sampled rows and scale
+            grows = np.random.default_rng(8).choice(n, 64, replace=False).astype(np.int64)
+            t0 = time.perf_counter()
+            oracle.grad_rows(Y, grows, Sg)
+            t_it = (time.perf_counter() - t0) * (n / grows.size)
+            it_desc = f"per-row gradient parts on {grows.size} of {n} rows (time x{n // grows.size}) per iteration"
+        else:
+            U = np.zeros_like(Y)
+            G = np.ones_like(Y)
+            t0 = time.perf_counter()
+            for t in range(args.cpu_iters):
+                a, m = oracle.tsne_schedule(t, w.exaggeration, w.exaggeration_iters, w.momentum_early,
+                                            w.momentum_late)
+                g, _, _ = oracle.kl_grad(Y, Sg, a, want_kl=False)
+                oracle.step(Y, U, G, g, w.lr, m)
+            t_it = (time.perf_counter() - t0) / args.cpu_iters
+            it_desc = f"{args.cpu_iters} of {iters} gradient+step iterations (time x{iters / args.cpu_iters:g})"
         t_total = t_knn + t_ps + t_it * iters
         cpu = {"value": pairs_per_step / t_total, "unit": "pair interactions/s", "cores": thr, "kind": "oracle",
                "sample": (f"FP64 oracle, {thr} threads: exact kNN on {qrows.size} of {n} query rows (time x"
-                          f"{n // qrows.size}); calibration + symmetrisation of a full-size seeded k={w.k} graph; "
-                          f"{args.cpu_iters} of {iters} gradient+step iterations (time x{iters / args.cpu_iters:g}); "
-                          f"host {platform.processor() or platform.machine()}"),
+                          f"{n / qrows.size:g}); calibration + symmetrisation of a full-size seeded k={w.k} graph; "
+                          f"{it_desc}; host {platform.processor() or platform.machine()}"),
                "s_per_step_extrapolated": t_total}
         # errors vs FP64 from identical inputs
         g_idx = idx.cpu().numpy()[qrows]
@@ -236,7 +268,7 @@ def main():
             np.max(np.abs(ddq[same] - od[same]) / np.maximum(od[same], 1e-30)))
         Pd = api.SparseP(torch.from_numpy(Sg.row_ptr).to(dev), torch.from_numpy(Sg.col).to(dev),
                          torch.from_numpy(Sg.val.astype(np.float32)).to(dev), None, n)
-        for ystd, a in ((0.01, 12.0), (20.0, 1.0)):
+        for ystd, a in (((0.01, 12.0), (20.0, 1.0)) if not big else ()):
             Yt = synth.random_embedding(n, ystd, 99)
             gg, Zg, klg, _ = api.kl_grad(torch.from_numpy(Yt).to(dev), Pd, a, want_Z=True, want_kl=True)
             go, Zo, klo = oracle.kl_grad(Yt.astype(np.float64), Sg, a)
@@ -269,7 +301,7 @@ def main():
                                f"{iters} iterations",
                    "n": n, "d": w.d, "k": w.k, "perplexity": w.perplexity, "iters": iters, "knn": w.knn},
         "kl_grad_pairs_per_s": float(n) * (n - 1) / (grad_ms_mean * 1e-3),
-        "knn_build_s": {"fp32_exact_in_step": knn_fp32_s, **knn_cmp},
+        "knn_build_s": {f"{w.knn}_in_step": knn_fp32_s, **knn_cmp},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "errors_vs_fp64": errors,

@@ -182,6 +182,39 @@ int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_
 int tsne_step(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr, float momentum,
               float gain_inc, float gain_dec, float min_gain, void* stream);
 
+/* Optimiser schedule of tsne_optimize [vdMH08 Sec. 3.4, Algorithm 1; Jac88]. */
+typedef struct tsne_schedule {
+  float lr;                   /* learning rate (200) */
+  float exaggeration;         /* alpha while t < exaggeration_iters (12) */
+  int32_t exaggeration_iters; /* (100) */
+  float momentum_early;       /* momentum while t < exaggeration_iters (0.5) */
+  float momentum_late;        /* momentum afterwards (0.8) */
+  float gain_inc;             /* (0.2) */
+  float gain_dec;             /* (0.8) */
+  float min_gain;             /* (0.01) */
+} tsne_schedule;
+
+/*
+ * tsne_optimize -- iterations t = t_begin .. t_end - 1 of the optimiser
+ * [vdMH08 Algorithm 1], enqueued from native code: per iteration the kernels
+ * of tsne_kl_grad with alpha_t = (t < exaggeration_iters ? exaggeration : 1),
+ * then those of tsne_step with momentum_t = (t < exaggeration_iters ?
+ * momentum_early : momentum_late).  Bitwise identical to calling the two
+ * entry points in a loop.
+ *   Y, update, gains  [n][2] float, updated in place.  P as for tsne_kl_grad.
+ *   schedule  host pointer, read before the call returns.
+ *   kl_log    device double array of (t_end - t_begin) entries (nullable):
+ *             with log_every > 0, entry t - t_begin receives KL(P||Q) for the
+ *             iterations with (t + 1) % log_every == 0; others are untouched.
+ *   events    host array of 2 (t_end - t_begin) hipEvent_t handles (nullable;
+ *             NULL entries skipped): events[2 (t - t_begin)] and [.. + 1] are
+ *             recorded on `stream` right before and after iteration t's
+ *             gradient kernels, for timing.
+ */
+int tsne_optimize(float* Y, float* update, float* gains, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                  const float* val, int32_t t_begin, int32_t t_end, const tsne_schedule* schedule, int32_t log_every,
+                  double* kl_log, void* const* events, void* workspace, size_t* workspace_bytes, void* stream);
+
 /*
  * Differentiation form.  KL(P||Q) as a function of the embedding Y and of
  * the stored values p_e of a CSR P whose pattern is symmetric (tpos valid);

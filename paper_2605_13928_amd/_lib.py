@@ -28,6 +28,15 @@ _i32 = C.c_int32
 _f32 = C.c_float
 _szp = C.POINTER(C.c_size_t)
 
+
+class Schedule(C.Structure):
+    """tsne_schedule (include/tsne_mi355x.h)."""
+
+    _fields_ = [("lr", C.c_float), ("exaggeration", C.c_float), ("exaggeration_iters", C.c_int32),
+                ("momentum_early", C.c_float), ("momentum_late", C.c_float), ("gain_inc", C.c_float),
+                ("gain_dec", C.c_float), ("min_gain", C.c_float)]
+
+
 # name -> (restype, argtypes), in header order
 SIGNATURES = {
     "tsne_abi_version": (C.c_int, []),
@@ -38,6 +47,8 @@ SIGNATURES = {
     "tsne_symmetrize": (C.c_int, [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_kl_grad": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_step": (C.c_int, [_p, _p, _p, _p, _i64, _f32, _f32, _f32, _f32, _f32, _p]),
+    "tsne_optimize": (C.c_int, [_p, _p, _p, _i64, _p, _p, _p, _i32, _i32, C.POINTER(Schedule), _i32, _p, _p, _p,
+                                _szp, _p]),
     "tsne_kl_forward": (C.c_int, [_i32, _p, _i64, _p, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_kl_backward": (C.c_int, [_i32, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _szp, _p]),
 }

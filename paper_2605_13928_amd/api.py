@@ -16,13 +16,14 @@ import torch
 from . import _lib
 from ._lib import check
 
-# Algorithmic flops per ordered pair (i, j) of the all-pairs evaluation in
-# tsne_kl_grad: 2 sub, 2 fma (1 + dx^2 + dy^2), 1 reciprocal, 1 add (Z),
-# 1 mul (w^2), 2 fma (force) = 13.
-KLGRAD_FLOPS_PER_ORDERED_PAIR = 13.0
+# Algorithmic flops of the all-pairs evaluation in tsne_kl_grad.  Each
+# unordered pair {i, j} is evaluated once and feeds both rows: 2 sub,
+# 2 fma (1 + dx^2 + dy^2), 1 reciprocal, 1 add (Z), 1 mul (w^2), 4 fma
+# (force on i and on j) = 17 flops, i.e. 8.5 per ordered pair.
+KLGRAD_FLOPS_PER_ORDERED_PAIR = 8.5
 
-__all__ = ["knn", "calibrate_P", "symmetrize", "kl_grad", "step", "kl_forward", "kl_backward", "SparseP",
-           "Workspace"]
+__all__ = ["knn", "calibrate_P", "symmetrize", "kl_grad", "step", "optimize", "kl_forward", "kl_backward",
+           "SparseP", "Workspace"]
 
 
 def _ptr(t):
@@ -179,6 +180,42 @@ def step(Y, update, gains, grad, lr: float, momentum: float, gain_inc: float = 0
     L = _lib.load()
     check("tsne_step", L.tsne_step(_ptr(Y), _ptr(update), _ptr(gains), _ptr(grad), n, float(lr), float(momentum),
                                    float(gain_inc), float(gain_dec), float(min_gain), _stream(Y.device)))
+
+
+def optimize(Y, update, gains, P: SparseP, t_begin: int, t_end: int, lr: float = 200.0, exaggeration: float = 12.0,
+             exaggeration_iters: int = 100, momentum_early: float = 0.5, momentum_late: float = 0.8,
+             gain_inc: float = 0.2, gain_dec: float = 0.8, min_gain: float = 0.01, log_every: int = 0,
+             kl_log: torch.Tensor | None = None, events=None, ws: Workspace | None = None):
+    """Iterations t_begin .. t_end-1 (gradient + step each) enqueued by the library.
+
+    kl_log: float64 device tensor of t_end - t_begin entries (KL written at
+    iterations with (t + 1) % log_every == 0).  events: optional list of
+    2 (t_end - t_begin) torch.cuda.Event (recorded around each gradient).
+    """
+    n = Y.shape[0]
+    for t, name in ((Y, "Y"), (update, "update"), (gains, "gains")):
+        _req(t, name, torch.float32, (n, 2))
+    if P.n != n:
+        raise ValueError("P does not match Y")
+    iters = t_end - t_begin
+    if kl_log is not None:
+        _req(kl_log, "kl_log", torch.float64, (iters,))
+    ev_arr = None
+    if events is not None:
+        if len(events) != 2 * iters:
+            raise ValueError("need two events per iteration")
+        handles = [int(e.cuda_event) for e in events]
+        if not all(handles):
+            raise ValueError("events must have been created (record each once) before use")
+        ev_arr = C.cast((C.c_void_p * (2 * iters))(*handles), C.c_void_p)
+    sc = _lib.Schedule(lr, exaggeration, exaggeration_iters, momentum_early, momentum_late, gain_inc, gain_dec,
+                       min_gain)
+    dev = Y.device
+    L = _lib.load()
+    _run_with_workspace("tsne_optimize", L.tsne_optimize,
+                        (_ptr(Y), _ptr(update), _ptr(gains), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val),
+                         int(t_begin), int(t_end), C.byref(sc), int(log_every), _ptr(kl_log), ev_arr),
+                        (_stream(dev),), dev, ws, key=("optimize", n))
 
 
 def _dtype_code(t):

@@ -6,6 +6,7 @@
 // g_i = 4 (alpha A_i - R_i / Z); and, when KL is requested, a one-block
 // reduction of the per-block sums p ln p, p ln q (q = 1/w) and p.
 #include "common.hpp"
+#include "klgrad.hpp"
 #include "rep_sym.hpp"
 
 namespace tsne {
@@ -145,6 +146,47 @@ __global__ __launch_bounds__(256) void kl_reduce_kernel(const double* __restrict
   if (threadIdx.x == 0) *kl_out = a + b + c * log(Z);
 }
 
+KlGradPlan klgrad_plan(int64_t n) {
+  KlGradPlan L;
+  L.g = SymGrid::make(n);
+  L.nfin = ceil_div(n, FIN_ROWS);
+  Carve c;
+  L.o_R = c.take(sizeof(float2) * size_t(L.g.ns) * size_t(n));
+  L.o_Zr = c.take(sizeof(float) * size_t(L.g.ns) * size_t(n));
+  L.o_Zb = c.take(sizeof(double) * size_t(L.g.nwg));
+  L.o_kl = c.take(sizeof(double) * 3 * size_t(L.nfin));
+  L.bytes = c.off;
+  return L;
+}
+
+int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, const int64_t* row_ptr,
+                  const int32_t* col, const float* val, float alpha, float* grad, double* Z, double* kl, double* Zrow,
+                  hipStream_t s) {
+  const SymGrid& g = L.g;
+  float* Rpart = reinterpret_cast<float*>(ws + L.o_R);
+  float* Zrowpart = Zrow ? reinterpret_cast<float*>(ws + L.o_Zr) : nullptr;
+  double* Zblock = reinterpret_cast<double*>(ws + L.o_Zb);
+  double* klpart = kl ? reinterpret_cast<double*>(ws + L.o_kl) : nullptr;
+  const float2* Y2 = reinterpret_cast<const float2*>(Y);
+  const size_t lds = rep_sym_lds_bytes(g.S, Zrow != nullptr);
+  if (Zrow)
+    hipLaunchKernelGGL(rep_sym_kernel<true>, dim3(unsigned(g.nwg)), dim3(256), lds, s, Y2, n, int(g.S), g.ns, Rpart,
+                       Zrowpart, Zblock);
+  else
+    hipLaunchKernelGGL(rep_sym_kernel<false>, dim3(unsigned(g.nwg)), dim3(256), lds, s, Y2, n, int(g.S), g.ns, Rpart,
+                       Zrowpart, Zblock);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(finalize_tsne_kernel, dim3(unsigned(L.nfin)), dim3(256), 0, s, Y2, n, row_ptr, col, val, alpha,
+                     reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, Zblock, g.nwg,
+                     reinterpret_cast<float2*>(grad), Zrow, Z, klpart);
+  TSNE_CHECK_LAUNCH();
+  if (kl) {
+    hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, klpart, L.nfin, Zblock, g.nwg, kl);
+    TSNE_CHECK_LAUNCH();
+  }
+  return TSNE_OK;
+}
+
 }  // namespace tsne
 
 extern "C" int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
@@ -154,38 +196,9 @@ extern "C" int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, c
   if (!Y || !row_ptr || !col || !val || !grad || n < 2) return TSNE_ERR_INVALID_ARG;
   if (!(exaggeration > 0.0f) || !(exaggeration < INFINITY)) return TSNE_ERR_INVALID_ARG;
   if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
-  const SymGrid g = SymGrid::make(n);
-  const int64_t nfin = ceil_div(n, FIN_ROWS);
-  Carve c;
-  const size_t o_R = c.take(sizeof(float2) * size_t(g.ns) * size_t(n));
-  const size_t o_Zr = c.take(sizeof(float) * size_t(g.ns) * size_t(n));
-  const size_t o_Zb = c.take(sizeof(double) * size_t(g.nwg));
-  const size_t o_kl = c.take(sizeof(double) * 3 * size_t(nfin));
-  int rc = workspace_protocol(workspace, workspace_bytes, c.off);
+  const KlGradPlan L = klgrad_plan(n);
+  int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
-  char* ws = static_cast<char*>(workspace);
-  float* Rpart = reinterpret_cast<float*>(ws + o_R);
-  float* Zrowpart = Zrow ? reinterpret_cast<float*>(ws + o_Zr) : nullptr;
-  double* Zblock = reinterpret_cast<double*>(ws + o_Zb);
-  double* klpart = kl ? reinterpret_cast<double*>(ws + o_kl) : nullptr;
-  hipStream_t s = as_stream(stream);
-  const float2* Y2 = reinterpret_cast<const float2*>(Y);
-
-  const size_t lds = rep_sym_lds_bytes(g.S, Zrow != nullptr);
-  if (Zrow)
-    hipLaunchKernelGGL(rep_sym_kernel<true>, dim3(unsigned(g.nwg)), dim3(256), lds, s, Y2, n, int(g.S), g.ns, Rpart,
-                       Zrowpart, Zblock);
-  else
-    hipLaunchKernelGGL(rep_sym_kernel<false>, dim3(unsigned(g.nwg)), dim3(256), lds, s, Y2, n, int(g.S), g.ns, Rpart,
-                       Zrowpart, Zblock);
-  TSNE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(finalize_tsne_kernel, dim3(unsigned(nfin)), dim3(256), 0, s, Y2, n, row_ptr, col, val, exaggeration,
-                     reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, Zblock, g.nwg,
-                     reinterpret_cast<float2*>(grad), Zrow, Z, klpart);
-  TSNE_CHECK_LAUNCH();
-  if (kl) {
-    hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, klpart, nfin, Zblock, g.nwg, kl);
-    TSNE_CHECK_LAUNCH();
-  }
-  return TSNE_OK;
+  return klgrad_launch(L, static_cast<char*>(workspace), Y, n, row_ptr, col, val, exaggeration, grad, Z, kl, Zrow,
+                       as_stream(stream));
 }

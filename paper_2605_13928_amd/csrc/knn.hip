@@ -84,22 +84,48 @@ constexpr int F_RW = 16;
 constexpr int F_ROWS = 64;
 constexpr int F_COLS = 128;
 constexpr int F_DC = 64;
+constexpr int XI_S = F_ROWS + 4;  // LDS row strides: multiples of 4 floats keep the
+constexpr int XJ_S = F_COLS + 4;  // 16-byte reads aligned and spread the stores' banks
+
+// Stage rows [r0, r0 + nrows) x dims [dc, dc + dl) of X transposed into
+// dst[c * stride + r]: one row per wave instruction (coalesced), rows past
+// n as zeros.
+__device__ __forceinline__ void stage_rows_t(float* __restrict__ dst, int stride, const float* __restrict__ X,
+                                             int64_t r0, int nrows, int64_t n, int d, int dc, int dl) {
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  for (int r = w; r < nrows; r += 16) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = r + 4 * u;
+      const int64_t g = r0 + rr;
+      v[u] = (rr < nrows && g < n && lane < dl) ? X[g * d + dc + lane] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = r + 4 * u;
+      if (rr < nrows && lane < dl) dst[lane * stride + rr] = v[u];
+    }
+  }
+}
 
 template <int EPL>
 __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__ X, int64_t n, int d, int k,
                                                        uint64_t* __restrict__ bufs, int32_t* __restrict__ out_idx,
                                                        float* __restrict__ out_d2) {
   constexpr int CAP = 64 * EPL;
-  __shared__ __attribute__((aligned(16))) float xi_s[F_DC][F_ROWS];
-  __shared__ __attribute__((aligned(16))) float xj_s[F_DC][F_COLS];
+  __shared__ __attribute__((aligned(16))) float xi_s[F_DC * XI_S];
+  __shared__ __attribute__((aligned(16))) float xj_s[F_DC * XJ_S];
   __shared__ int cnt_s[F_ROWS];
   __shared__ float tau_s[F_ROWS];
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int64_t row0 = int64_t(blockIdx.x) * F_ROWS;
   if (tid < F_ROWS) {
     cnt_s[tid] = 0;
-    tau_s[tid] = INFINITY;
+    tau_s[tid] = row0 + tid < n ? INFINITY : -INFINITY;  // rows past n never accept
   }
+  const bool one_chunk = d <= F_DC;
+  if (one_chunk) stage_rows_t(xi_s, XI_S, X, row0, F_ROWS, n, d, 0, d);
   for (int64_t c0 = 0; c0 < n; c0 += F_COLS) {
     float acc[F_RW][2];
 #pragma unroll
@@ -107,23 +133,15 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
     for (int dc = 0; dc < d; dc += F_DC) {
       const int dl = (d - dc) < F_DC ? (d - dc) : F_DC;
       __syncthreads();
-      for (int u = tid; u < F_ROWS * dl; u += 256) {
-        const int r = u / dl, c = u - r * dl;
-        const int64_t g = row0 + r;
-        xi_s[c][r] = g < n ? X[g * d + dc + c] : 0.0f;
-      }
-      for (int u = tid; u < F_COLS * dl; u += 256) {
-        const int jj = u / dl, c = u - jj * dl;
-        const int64_t g = c0 + jj;
-        xj_s[c][jj] = g < n ? X[g * d + dc + c] : 0.0f;
-      }
+      if (!one_chunk) stage_rows_t(xi_s, XI_S, X, row0, F_ROWS, n, d, dc, dl);
+      stage_rows_t(xj_s, XJ_S, X, c0, F_COLS, n, d, dc, dl);
       __syncthreads();
       for (int c = 0; c < dl; ++c) {
-        const float4* ap = reinterpret_cast<const float4*>(&xi_s[c][w * F_RW]);
+        const float4* ap = reinterpret_cast<const float4*>(&xi_s[c * XI_S + w * F_RW]);
         const float4 a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
         const float a[F_RW] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
                                a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
-        const float2 b = *reinterpret_cast<const float2*>(&xj_s[c][lane * 2]);
+        const float2 b = *reinterpret_cast<const float2*>(&xj_s[c * XJ_S + lane * 2]);
 #pragma unroll
         for (int r = 0; r < F_RW; ++r) {
           const float t0 = a[r] - b.x, t1 = a[r] - b.y;
@@ -132,30 +150,41 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
         }
       }
     }
-    // filter + append
+    // filter: one compare per candidate; the append path (and, only in the
+    // tail step and the step holding the block's own rows, the index checks)
+    // runs when some lane has a candidate at or below its row's threshold
+    float tau[F_RW];
+    bool any = false;
 #pragma unroll
     for (int r = 0; r < F_RW; ++r) {
-      const int lr = w * F_RW + r;
-      const int64_t gi = row0 + lr;
-      const float tau = tau_s[lr];
+      tau[r] = tau_s[w * F_RW + r];
+      any |= (acc[r][0] <= tau[r]) | (acc[r][1] <= tau[r]);
+    }
+    if (__ballot(any)) {
+      const bool edge = (c0 + F_COLS > n) || (c0 < row0 + F_ROWS && row0 < c0 + F_COLS);
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int64_t j = c0 + lane * 2 + u;
-        const float dd = acc[r][u];
-        if (gi < n && j < n && j != gi && dd <= tau) {
-          const int pos = atomicAdd(&cnt_s[lr], 1);
-          bufs[gi * CAP + pos] = make_key(dd, int32_t(j));
+      for (int r = 0; r < F_RW; ++r) {
+        const int lr = w * F_RW + r;
+        const int64_t gi = row0 + lr;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int64_t j = c0 + lane * 2 + u;
+          const float dd = acc[r][u];
+          if (dd <= tau[r] && (!edge || (j < n && j != gi))) {
+            const int pos = atomicAdd(&cnt_s[lr], 1);
+            bufs[gi * CAP + pos] = make_key(dd, int32_t(j));
+          }
         }
       }
-    }
-    // compaction of rows that could overflow in the next step
-    const int cl = lane < F_RW ? cnt_s[w * F_RW + lane] : 0;
-    uint64_t need = __ballot(lane < F_RW && cl > CAP - F_COLS);
-    while (need) {
-      const int r = __ffsll((unsigned long long)need) - 1;
-      need &= need - 1;
-      const int lr = w * F_RW + r;
-      compact_row<EPL>(bufs + (row0 + lr) * CAP, &cnt_s[lr], &tau_s[lr], k);
+      // compaction of rows that could overflow in the next step
+      const int cl = lane < F_RW ? cnt_s[w * F_RW + lane] : 0;
+      uint64_t need = __ballot(lane < F_RW && cl > CAP - F_COLS);
+      while (need) {
+        const int r = __ffsll((unsigned long long)need) - 1;
+        need &= need - 1;
+        const int lr = w * F_RW + r;
+        compact_row<EPL>(bufs + (row0 + lr) * CAP, &cnt_s[lr], &tau_s[lr], k);
+      }
     }
   }
   for (int r = 0; r < F_RW; ++r) {
@@ -225,16 +254,18 @@ __global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__
                                                        int64_t n, int ncand, uint64_t* __restrict__ bufs,
                                                        int32_t* __restrict__ cand) {
   constexpr int CAP = 64 * EPL;
-  __shared__ uint4 tile[B_TJ * 8];  // 64 rows x 128 bytes
+  __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
   __shared__ int cnt_s[256];
   __shared__ float tau_s[256];
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-  const int64_t qbase = int64_t(blockIdx.x) * 256 + w * 64;
+  const int64_t qblock = int64_t(blockIdx.x) * 256;
+  const int64_t qbase = qblock + w * 64;
   cnt_s[tid] = 0;
   tau_s[tid] = INFINITY;
   // query fragments: tile t, k-step s; lane holds query qbase + 16 t + lane % 16,
   // k elements 32 s + 8 (lane / 16) ... + 7
   bf16x8_t bq[4][2];
+  float tau[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int64_t qi = qbase + t * 16 + (lane & 15);
@@ -244,35 +275,63 @@ __global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__
       if (qi < n) v = Xq[qi * 8 + s * 4 + (lane >> 4)];
       bq[t][s] = __builtin_bit_cast(bf16x8_t, v);
     }
+    tau[t] = qi < n ? INFINITY : -INFINITY;  // queries past n never accept
   }
-  float tau[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  // prefetch tile 0
+  uint4 nxt[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int u = tid + 256 * h;
+    const int64_t g = u >> 3;
+    nxt[h] = g < n ? Xc[g * 8 + (u & 7)] : make_uint4(0, 0, 0, 0);
+  }
+  int buf = 0;
   for (int64_t c0 = 0; c0 < n; c0 += B_TJ) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) tile[buf][tid + 256 * h] = nxt[h];
     __syncthreads();
-    for (int u = tid; u < B_TJ * 8; u += 256) {
-      const int64_t g = c0 + (u >> 3);
-      tile[u] = g < n ? Xc[g * 8 + (u & 7)] : make_uint4(0, 0, 0, 0);
+    // fetch the next tile while this one is consumed
+    if (c0 + B_TJ < n) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int u = tid + 256 * h;
+        const int64_t g = c0 + B_TJ + (u >> 3);
+        nxt[h] = g < n ? Xc[g * 8 + (u & 7)] : make_uint4(0, 0, 0, 0);
+      }
     }
-    __syncthreads();
+    const uint4* tl = tile[buf];
+    const bool edge = (c0 + B_TJ > n) || (c0 < qblock + 256 && qblock < c0 + B_TJ);
 #pragma unroll
     for (int sub = 0; sub < B_TJ / 16; ++sub) {
       const int rloc = sub * 16 + (lane & 15);
-      const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, tile[rloc * 8 + (lane >> 4)]);
-      const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, tile[rloc * 8 + 4 + (lane >> 4)]);
+      const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, tl[rloc * 8 + (lane >> 4)]);
+      const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, tl[rloc * 8 + 4 + (lane >> 4)]);
+      floatx4_t acc[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        floatx4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bq[t][0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bq[t][1], acc, 0, 0, 0);
-        // acc[r] = distance(query qbase + 16 t + lane % 16, candidate c0 + 16 sub + 4 (lane / 16) + r)
-        const int64_t qi = qbase + t * 16 + (lane & 15);
+        acc[t] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bq[t][0], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bq[t][1], acc[t], 0, 0, 0);
+      }
+      // acc[t][r] = distance(query qbase + 16 t + lane % 16, candidate c0 + 16 sub + 4 (lane / 16) + r)
+      bool any = false;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t j = c0 + sub * 16 + 4 * (lane >> 4) + r;
-          const float dd = acc[r];
-          if (dd <= tau[t] && j < n && j != qi && qi < n) {
-            const int lq = w * 64 + t * 16 + (lane & 15);
-            const int pos = atomicAdd(&cnt_s[lq], 1);
-            bufs[qi * CAP + pos] = make_key(fmaxf(dd, 0.0f), int32_t(j));
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) any |= acc[t][r] <= tau[t];
+      if (__ballot(any)) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t qi = qbase + t * 16 + (lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t j = c0 + sub * 16 + 4 * (lane >> 4) + r;
+            const float dd = acc[t][r];
+            if (dd <= tau[t] && (!edge || (j < n && j != qi))) {
+              const int lq = w * 64 + t * 16 + (lane & 15);
+              const int pos = atomicAdd(&cnt_s[lq], 1);
+              bufs[qi * CAP + pos] = make_key(fmaxf(dd, 0.0f), int32_t(j));
+            }
           }
         }
       }
@@ -287,8 +346,12 @@ __global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__
         compact_row<EPL>(bufs + (qbase + r) * CAP, &cnt_s[lq], &tau_s[lq], ncand);
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) tau[t] = tau_s[w * 64 + t * 16 + (lane & 15)];
+      for (int t = 0; t < 4; ++t) {
+        const int64_t qi = qbase + t * 16 + (lane & 15);
+        tau[t] = qi < n ? tau_s[w * 64 + t * 16 + (lane & 15)] : -INFINITY;
+      }
     }
+    buf ^= 1;
   }
   for (int r = 0; r < 64; ++r) {
     const int64_t qi = qbase + r;
@@ -340,7 +403,7 @@ struct KnnLayout {
     KnnLayout L;
     Carve c;
     if (precision == TSNE_KNN_FP32) {
-      L.epl = k <= 128 ? 4 : 8;
+      L.epl = 8;  // capacity 512: room for 384 appends between compactions
       L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * size_t(64 * L.epl));
       L.o_xq = L.o_xc = L.o_cand = 0;
     } else {
@@ -374,10 +437,7 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   hipStream_t s = as_stream(stream);
   if (precision == TSNE_KNN_FP32) {
     const dim3 grid(unsigned(ceil_div(n, F_ROWS)));
-    if (L.epl == 4)
-      hipLaunchKernelGGL(knn_fp32_kernel<4>, grid, dim3(256), 0, s, X, n, d, k, bufs, nbr_idx, nbr_d2);
-    else
-      hipLaunchKernelGGL(knn_fp32_kernel<8>, grid, dim3(256), 0, s, X, n, d, k, bufs, nbr_idx, nbr_d2);
+    hipLaunchKernelGGL(knn_fp32_kernel<8>, grid, dim3(256), 0, s, X, n, d, k, bufs, nbr_idx, nbr_d2);
     TSNE_CHECK_LAUNCH();
     return TSNE_OK;
   }

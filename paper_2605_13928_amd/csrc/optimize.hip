@@ -1,0 +1,50 @@
+// tsne_optimize: a run of optimiser iterations enqueued from native code --
+// per iteration one gradient evaluation (tsne_kl_grad's kernels) and one
+// step (tsne_step's kernel), with the schedule of van der Maaten & Hinton
+// 2008 (Sec. 3.4, Algorithm 1): early exaggeration and the lower momentum
+// while t < exaggeration_iters.  Same kernels and arithmetic as the separate
+// calls, so results are bitwise identical to calling them in a loop.
+#include "common.hpp"
+#include "klgrad.hpp"
+
+extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, const int64_t* row_ptr,
+                             const int32_t* col, const float* val, int32_t t_begin, int32_t t_end,
+                             const tsne_schedule* schedule, int32_t log_every, double* kl_log, void* const* events,
+                             void* workspace, size_t* workspace_bytes, void* stream) {
+  using namespace tsne;
+  if (!Y || !update || !gains || !row_ptr || !col || !val || !schedule || n < 2) return TSNE_ERR_INVALID_ARG;
+  if (t_begin < 0 || t_end < t_begin || log_every < 0) return TSNE_ERR_INVALID_ARG;
+  const tsne_schedule sc = *schedule;
+  if (!(sc.exaggeration > 0.0f) || !(sc.exaggeration < INFINITY) || !(sc.lr > 0.0f)) return TSNE_ERR_INVALID_ARG;
+  if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
+  const KlGradPlan L = klgrad_plan(n);
+  Carve c;
+  const size_t o_kg = c.take(L.bytes);
+  const size_t o_g = c.take(sizeof(float) * 2 * size_t(n));
+  int rc = workspace_protocol(workspace, workspace_bytes, c.off);
+  if (rc >= 0) return rc;
+  char* ws = static_cast<char*>(workspace);
+  float* grad = reinterpret_cast<float*>(ws + o_g);
+  hipStream_t s = as_stream(stream);
+  for (int32_t t = t_begin; t < t_end; ++t) {
+    const bool early = t < sc.exaggeration_iters;
+    const float alpha = early ? sc.exaggeration : 1.0f;
+    const float mom = early ? sc.momentum_early : sc.momentum_late;
+    const bool log = kl_log && log_every > 0 && (t + 1) % log_every == 0;
+    const int64_t slot = int64_t(t - t_begin);
+    if (events && events[2 * slot]) {
+      const hipError_t e = hipEventRecord(static_cast<hipEvent_t>(events[2 * slot]), s);
+      if (e != hipSuccess) { set_last_hip_error(e); return TSNE_ERR_HIP; }
+    }
+    rc = klgrad_launch(L, ws + o_kg, Y, n, row_ptr, col, val, alpha, grad, nullptr, log ? kl_log + slot : nullptr,
+                       nullptr, s);
+    if (rc) return rc;
+    if (events && events[2 * slot + 1]) {
+      const hipError_t e = hipEventRecord(static_cast<hipEvent_t>(events[2 * slot + 1]), s);
+      if (e != hipSuccess) { set_last_hip_error(e); return TSNE_ERR_HIP; }
+    }
+    rc = step_launch(Y, update, gains, grad, n, sc.lr, mom, sc.gain_inc, sc.gain_dec, sc.min_gain, s);
+    if (rc) return rc;
+  }
+  return TSNE_OK;
+}

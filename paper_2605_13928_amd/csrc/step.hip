@@ -2,6 +2,7 @@
 // (van der Maaten & Hinton 2008, Algorithm 1; Jacobs 1988 gains).
 // HBM-bound elementwise pass: 28 bytes in + 24 bytes out per point.
 #include "common.hpp"
+#include "klgrad.hpp"
 
 namespace tsne {
 
@@ -28,15 +29,21 @@ __global__ __launch_bounds__(256) void step_kernel(float2* __restrict__ Y, float
   G[i] = ga;
 }
 
+int step_launch(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr, float momentum,
+                float gain_inc, float gain_dec, float min_gain, hipStream_t s) {
+  hipLaunchKernelGGL(step_kernel, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s, reinterpret_cast<float2*>(Y),
+                     reinterpret_cast<float2*>(update), reinterpret_cast<float2*>(gains),
+                     reinterpret_cast<const float2*>(grad), n, lr, momentum, gain_inc, gain_dec, min_gain);
+  TSNE_CHECK_LAUNCH();
+  return TSNE_OK;
+}
+
 }  // namespace tsne
 
 extern "C" int tsne_step(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr,
                          float momentum, float gain_inc, float gain_dec, float min_gain, void* stream) {
   if (!Y || !update || !gains || !grad || n < 1) return TSNE_ERR_INVALID_ARG;
   if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
-  hipLaunchKernelGGL(tsne::step_kernel, dim3(unsigned(tsne::ceil_div(n, 256))), dim3(256), 0, tsne::as_stream(stream),
-                     reinterpret_cast<float2*>(Y), reinterpret_cast<float2*>(update), reinterpret_cast<float2*>(gains),
-                     reinterpret_cast<const float2*>(grad), n, lr, momentum, gain_inc, gain_dec, min_gain);
-  TSNE_CHECK_LAUNCH();
-  return TSNE_OK;
+  return tsne::step_launch(Y, update, gains, grad, n, lr, momentum, gain_inc, gain_dec, min_gain,
+                           tsne::as_stream(stream));
 }

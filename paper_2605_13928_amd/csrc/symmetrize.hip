@@ -5,7 +5,9 @@
 //   1. in-degree histogram (integer atomics), exclusive scan -> in_ptr
 //   2. scatter (source, p) into the transposed lists (atomic cursors give an
 //      arbitrary order) ...
-//   3. ... which a per-row rank sort (one wave per row) makes canonical
+//   3. ... which a per-row sort (one wave per row: register bitonic sort of
+//      (source, value) keys up to 1024 entries, a rank sort beyond) makes
+//      canonical
 //   4. rank-sort each row's k out-entries by column
 //   5. union size per row (binary search of each out-entry in the in-list),
 //      scan -> row_ptr
@@ -174,6 +176,39 @@ __device__ void wave_rank_sort_segment(const int32_t* __restrict__ key, const fl
   }
 }
 
+// Bitonic variant for segments of at most EPL*64 entries: keys are
+// (source << 32 | value bits); sources in one in-list are distinct for valid
+// input, so the order is by source.  A repeated source (invalid input) is
+// reported through err.
+template <int EPL>
+__device__ void wave_bitonic_segment(const int32_t* __restrict__ key, const float* __restrict__ val, int64_t len,
+                                     int32_t* __restrict__ okey, float* __restrict__ oval, int* __restrict__ err) {
+  const int lane = lane_id();
+  uint64_t v[EPL];
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int e = t * 64 + lane;
+    v[t] = e < len ? ((uint64_t(uint32_t(key[e])) << 32) | __float_as_uint(val[e])) : KEY_MAX;
+  }
+  wave_sort<EPL>(v);
+  bool rep = false;
+  uint32_t prev_last = 0;
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int e = t * 64 + lane;
+    const uint32_t hi = uint32_t(v[t] >> 32);
+    uint32_t before = __shfl_up(hi, 1);  // source of element e - 1 (same register)
+    if (lane == 0) before = prev_last;   // ... or the last lane of the previous register
+    if (e > 0 && e < len && before == hi) rep = true;
+    prev_last = __builtin_amdgcn_readlane(hi, 63);
+    if (e < len) {
+      okey[e] = int32_t(hi);
+      oval[e] = __uint_as_float(uint32_t(v[t]));
+    }
+  }
+  if (rep) atomicOr(err, 1);
+}
+
 __global__ __launch_bounds__(256) void sym_sort_in_kernel(const int64_t* __restrict__ in_ptr,
                                                           const int32_t* __restrict__ in_src,
                                                           const float* __restrict__ in_val, int64_t n,
@@ -182,7 +217,13 @@ __global__ __launch_bounds__(256) void sym_sort_in_kernel(const int64_t* __restr
   const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const int64_t a = in_ptr[row], b = in_ptr[row + 1];
-  wave_rank_sort_segment(in_src + a, in_val + a, b - a, s_src + a, s_val + a, err);
+  const int64_t len = b - a;
+  if (len <= 256)
+    wave_bitonic_segment<4>(in_src + a, in_val + a, len, s_src + a, s_val + a, err);
+  else if (len <= 1024)
+    wave_bitonic_segment<16>(in_src + a, in_val + a, len, s_src + a, s_val + a, err);
+  else
+    wave_rank_sort_segment(in_src + a, in_val + a, len, s_src + a, s_val + a, err);
 }
 
 __global__ __launch_bounds__(256) void sym_sort_out_kernel(const int32_t* __restrict__ nbr,

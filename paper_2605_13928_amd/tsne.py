@@ -58,7 +58,23 @@ class State:
 
 def iterate(state: State, P: api.SparseP, w: Workload, iters: int, log_every: int = 0,
             ws: api.Workspace | None = None):
-    """Run `iters` iterations from state.t; KL (device scalar) every log_every iterations."""
+    """Run `iters` iterations from state.t in one native call (tsne_optimize);
+    KL every log_every iterations lands in state.kl as device scalars."""
+    t0, t1 = state.t, state.t + iters
+    kl_log = torch.zeros(iters, dtype=torch.float64, device=state.Y.device) if log_every > 0 else None
+    api.optimize(state.Y, state.update, state.gains, P, t0, t1, w.lr, w.exaggeration, w.exaggeration_iters,
+                 w.momentum_early, w.momentum_late, log_every=log_every, kl_log=kl_log, ws=ws)
+    if kl_log is not None:
+        for t in range(t0, t1):
+            if (t + 1) % log_every == 0:
+                state.kl[t] = kl_log[t - t0:t - t0 + 1]
+    state.t = t1
+    return state
+
+
+def iterate_calls(state: State, P: api.SparseP, w: Workload, iters: int, log_every: int = 0,
+                  ws: api.Workspace | None = None):
+    """The same iterations as separate tsne_kl_grad / tsne_step calls."""
     ws = ws or api.Workspace()
     for _ in range(iters):
         t = state.t

@@ -68,3 +68,28 @@ def test_resume_equals_straight_run(dev):
     tsne.iterate(a, A.P, w, 30)
     tsne.iterate(snap, A.P, w, 30)
     assert torch.equal(a.Y, snap.Y)
+
+
+def test_native_loop_equals_separate_calls(dev):
+    # tsne_optimize enqueues the same kernels as tsne_kl_grad + tsne_step
+    say("native loop vs calls")
+    w = synth.WORKLOADS["c1"]
+    X, labels = synth.make_points(w)
+    Y0 = to_dev(synth.make_init(w), dev)
+    A = tsne.affinities(to_dev(X, dev), w)
+    a = tsne.iterate(tsne.State.start(Y0), A.P, w, 130, log_every=50)
+    b = tsne.iterate_calls(tsne.State.start(Y0), A.P, w, 130, log_every=50)
+    assert torch.equal(a.Y, b.Y) and torch.equal(a.update, b.update) and torch.equal(a.gains, b.gains)
+    assert sorted(a.kl) == sorted(b.kl) == [49, 99]
+    for t in a.kl:
+        assert a.kl[t].item() == b.kl[t].item()
+    # timing hook: one event pair per iteration, recorded around the gradient
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(20)]
+    for e in evs:
+        e.record()
+    torch.cuda.synchronize()
+    st = tsne.State.start(Y0)
+    api.optimize(st.Y, st.update, st.gains, A.P, 0, 10, events=evs)
+    torch.cuda.synchronize()
+    ms = [evs[2 * i].elapsed_time(evs[2 * i + 1]) for i in range(10)]
+    assert all(m > 0 for m in ms)

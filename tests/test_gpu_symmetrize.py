@@ -45,23 +45,28 @@ def test_symmetrize_random_graphs(dev, n, k, seed):
 
 
 def test_symmetrize_hub_rows(dev):
-    # a few points are everybody's neighbour: long in-lists (> 256 entries)
+    # hubs with in-lists of ~300, ~900 and ~3000 entries exercise every
+    # per-row sort path (<= 256, <= 1024 and longer)
     say("symmetrize hubs")
     n, k = 3000, 20
-    idx, _ = synth.random_knn_graph(n, k, 9)
-    idx[:, 0] = np.where(np.arange(n) == 5, 6, 5)
-    idx[:, 1] = np.where(np.arange(n) == 7, 8, 7)
-    for i in range(n):  # keep rows free of repeats
-        row = idx[i]
-        rest = [j for j in row[2:] if j not in (5, 6, 7, 8)]
-        fill = [j for j in range(9, n) if j != i and j not in row][: k - 2 - len(rest)]
-        idx[i, 2:] = np.array(rest + fill, dtype=np.int32)
-    rng = np.random.default_rng(1)
+    rng = np.random.default_rng(9)
+    hubs = {5: 300, 7: 900, 11: n - 1}
+    idx = np.empty((n, k), np.int32)
+    for i in range(n):
+        row = [h for h, deg in hubs.items() if h != i and (deg == n - 1 or rng.random() < deg / n)]
+        pool = rng.permutation(n)
+        for j in pool:
+            if len(row) == k:
+                break
+            if j != i and j not in hubs and j not in row:
+                row.append(int(j))
+        idx[i] = row
     Pc = rng.random((n, k))
     Pc /= Pc.sum(1, keepdims=True)
     S, G = run_both(dev, idx, Pc)
     check(S, G, n)
-    assert np.diff(S.row_ptr)[5] > 2900
+    deg = np.diff(S.row_ptr)
+    assert deg[11] >= n - 1 and 200 < deg[5] < 400 and 700 < deg[7] < 1100
 
 
 def test_symmetrize_rejects_invalid_lists(dev):
