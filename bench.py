@@ -6,8 +6,8 @@ symmetrisation, then every gradient + optimiser iteration of the schedule.
 `value` = ordered pair interactions evaluated by the gradient over the timed
 steps / wall time of those steps.  The iterations run through tsne_optimize,
 which records HIP events (on the stream the kernels are launched on) right
-around each gradient evaluation: they give the dominant kernel's per-launch
-time for the roofline.  Outside the timed region: the BF16-MFMA vs FP32 kNN build
+around each launch of the all-pairs repulsion kernel: they give the dominant
+kernel's per-launch time for the roofline.  Outside the timed region: the BF16-MFMA vs FP32 kNN build
 comparison, and the CPU-baseline leg (the FP64 oracle timed on a bounded
 sample of the same workload, which also yields the error statistics).
 
@@ -119,9 +119,13 @@ def main():
         Pc, beta, conv, nun = api.calibrate_P(d2, w.perplexity)
         P = api.symmetrize(idx, Pc, want_tpos=False, ws=ws)
         st = tsne.State.start(Y0)
+        t2 = torch.cuda.Event(enable_timing=True)
+        t3 = torch.cuda.Event(enable_timing=True)
+        t2.record(stream)
         api.optimize(st.Y, st.update, st.gains, P, 0, iters, w.lr, w.exaggeration, w.exaggeration_iters,
                      w.momentum_early, w.momentum_late, events=events, ws=ws_opt)
-        return (t0, t1), st, P, idx, d2, Pc
+        t3.record(stream)
+        return (t0, t1, t2, t3), st, P, idx, d2, Pc
 
     for _ in range(args.warmup):
         one_step(None)
@@ -144,7 +148,8 @@ def main():
     pairs_per_step = float(n) * float(n - 1) * iters
     value = pairs_per_step * args.steps / elapsed
     grad_ms = np.array([ev[s][2 * i].elapsed_time(ev[s][2 * i + 1]) for s in range(args.steps) for i in range(iters)])
-    knn_fp32_s = float(np.median([a.elapsed_time(b) for a, b in knn_ev])) / 1e3
+    knn_fp32_s = float(np.median([e[0].elapsed_time(e[1]) for e in knn_ev])) / 1e3
+    iter_ms = float(np.median([e[2].elapsed_time(e[3]) for e in knn_ev])) / iters
     grad_ms_mean = float(grad_ms.mean())
     flops_per_call = api.KLGRAD_FLOPS_PER_ORDERED_PAIR * float(n) * float(n - 1)
     achieved_tflops = flops_per_call / (grad_ms_mean * 1e-3) / 1e12
@@ -280,7 +285,7 @@ def main():
 
     roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
-                "kernel": "tsne_kl_grad (all-pairs repulsion + CSR attraction/finalize)",
+                "kernel": "rep_sym_kernel (all-pairs Student-t repulsion and Z of tsne_kl_grad)",
                 "flops_per_call": flops_per_call, "ms_per_call": grad_ms_mean,
                 "flops_per_ordered_pair": api.KLGRAD_FLOPS_PER_ORDERED_PAIR, "source_digest": digest}
     rec = {
@@ -300,7 +305,9 @@ def main():
                                f"({w.weights} weights), perplexity {w.perplexity:g}, k={w.k}, {w.knn} kNN, "
                                f"{iters} iterations",
                    "n": n, "d": w.d, "k": w.k, "perplexity": w.perplexity, "iters": iters, "knn": w.knn},
-        "kl_grad_pairs_per_s": float(n) * (n - 1) / (grad_ms_mean * 1e-3),
+        "repulsion_pairs_per_s": float(n) * (n - 1) / (grad_ms_mean * 1e-3),
+        "iteration_ms": iter_ms,
+        "iteration_pairs_per_s": float(n) * (n - 1) / (iter_ms * 1e-3),
         "knn_build_s": {f"{w.knn}_in_step": knn_fp32_s, **knn_cmp},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -196,20 +196,25 @@ typedef struct tsne_schedule {
 
 /*
  * tsne_optimize -- iterations t = t_begin .. t_end - 1 of the optimiser
- * [vdMH08 Algorithm 1], enqueued from native code: per iteration the kernels
- * of tsne_kl_grad with alpha_t = (t < exaggeration_iters ? exaggeration : 1),
- * then those of tsne_step with momentum_t = (t < exaggeration_iters ?
- * momentum_early : momentum_late).  Bitwise identical to calling the two
- * entry points in a loop.
- *   Y, update, gains  [n][2] float, updated in place.  P as for tsne_kl_grad.
+ * [vdMH08 Algorithm 1], enqueued from native code: per iteration the
+ * gradient of tsne_kl_grad with alpha_t = (t < exaggeration_iters ?
+ * exaggeration : 1), then the update of tsne_step with momentum_t =
+ * (t < exaggeration_iters ? momentum_early : momentum_late).  The step runs
+ * inside the gradient's last pass, and Y alternates with a workspace copy
+ * (copied back at the end when the count is odd); the arithmetic is that of
+ * the two entry points, so the result is bitwise identical to calling them
+ * in a loop.
+ *   Y, update, gains  [n][2] float, updated in place (Y holds the result
+ *                     when the enqueued work completes).  P as for
+ *                     tsne_kl_grad.
  *   schedule  host pointer, read before the call returns.
  *   kl_log    device double array of (t_end - t_begin) entries (nullable):
  *             with log_every > 0, entry t - t_begin receives KL(P||Q) for the
  *             iterations with (t + 1) % log_every == 0; others are untouched.
  *   events    host array of 2 (t_end - t_begin) hipEvent_t handles (nullable;
  *             NULL entries skipped): events[2 (t - t_begin)] and [.. + 1] are
- *             recorded on `stream` right before and after iteration t's
- *             gradient kernels, for timing.
+ *             recorded on `stream` right before and right after iteration
+ *             t's all-pairs repulsion kernel (the dominant cost), for timing.
  */
 int tsne_optimize(float* Y, float* update, float* gains, int64_t n, const int64_t* row_ptr, const int32_t* col,
                   const float* val, int32_t t_begin, int32_t t_end, const tsne_schedule* schedule, int32_t log_every,

@@ -190,7 +190,8 @@ def optimize(Y, update, gains, P: SparseP, t_begin: int, t_end: int, lr: float =
 
     kl_log: float64 device tensor of t_end - t_begin entries (KL written at
     iterations with (t + 1) % log_every == 0).  events: optional list of
-    2 (t_end - t_begin) torch.cuda.Event (recorded around each gradient).
+    2 (t_end - t_begin) torch.cuda.Event (recorded around each launch of the
+    all-pairs repulsion kernel).
     """
     n = Y.shape[0]
     for t, name in ((Y, "Y"), (update, "update"), (gains, "gains")):

@@ -115,25 +115,22 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Fixed-order block reduction of one double per thread (blockDim.x = 256).
-// Result valid in every thread.
-__device__ __forceinline__ double block_sum_d(double v, double* lds /*256*/) {
-  lds[threadIdx.x] = v;
+// Fixed-order block reduction of one double per thread (blockDim.x = 256):
+// butterfly within each wave, then the four wave sums in order.  Result
+// valid (same bits) in every thread.  `lds` needs 4 doubles.
+__device__ __forceinline__ double block_sum_d(double v, double* lds) {
+  v = wave_sum_d(v);
+  if (lane_id() == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
-#pragma unroll
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) lds[threadIdx.x] = lds[threadIdx.x] + lds[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = lds[0];
+  const double r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
   __syncthreads();
   return r;
 }
 
 // Fixed-order sum of the per-block partials (Z), computed identically by
-// every block that needs it.
-__device__ __forceinline__ double sum_zblocks(const double* __restrict__ Zblock, int64_t nz, double* red) {
-  // eight independent loads in flight per thread, added in index order
+// every block that needs it: thread t adds entries t, t + 256, ... (eight
+// loads in flight), then the block reduction.
+__device__ __forceinline__ double zblock_thread_sum(const double* __restrict__ Zblock, int64_t nz) {
   double t = 0.0;
   int64_t b = threadIdx.x;
   for (; b + 7 * 256 < nz; b += 8 * 256) {
@@ -144,7 +141,10 @@ __device__ __forceinline__ double sum_zblocks(const double* __restrict__ Zblock,
     for (int u = 0; u < 8; ++u) t += v[u];
   }
   for (; b < nz; b += 256) t += Zblock[b];
-  return block_sum_d(t, red);
+  return t;
+}
+__device__ __forceinline__ double sum_zblocks(const double* __restrict__ Zblock, int64_t nz, double* red) {
+  return block_sum_d(zblock_thread_sum(Zblock, nz), red);
 }
 
 // ---------------------------------------------------------------------

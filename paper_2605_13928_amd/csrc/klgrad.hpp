@@ -6,6 +6,29 @@
 
 namespace tsne {
 
+// Momentum + adaptive-gains update of one coordinate (van der Maaten &
+// Hinton 2008, Algorithm 1; Jacobs 1988 gains): the gain grows by `inc` when
+// the gradient and the previous update have opposite signs, else shrinks by
+// the factor `dec`, floored at `mn`.
+__device__ __forceinline__ void step_coord(float& y, float& u, float& gain, float g, float lr, float mom, float inc,
+                                           float dec, float mn) {
+  float ng = (g * u < 0.0f) ? gain + inc : gain * dec;
+  ng = fmaxf(ng, mn);
+  u = mom * u - lr * ng * g;
+  y = y + u;
+  gain = ng;
+}
+
+// Optimiser step applied by the gradient's finalize pass: reads y_i from the
+// gradient's input Y and writes the stepped point to Yout (a different
+// buffer, since other rows still gather y_i in the same pass).
+struct FusedStep {
+  float2* Yout;
+  float2* U;
+  float2* G;
+  float lr, mom, inc, dec, mn;
+};
+
 struct KlGradPlan {
   SymGrid g;
   int64_t nfin;
@@ -16,9 +39,12 @@ struct KlGradPlan {
 KlGradPlan klgrad_plan(int64_t n);
 
 // Enqueue one gradient evaluation (arguments as tsne_kl_grad, validated).
+// With `step`, the finalize pass applies the optimiser step to every row
+// instead of writing the gradient (grad may then be null).  after_repulsion
+// (nullable) is recorded on s between the all-pairs pass and the finalize.
 int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, const int64_t* row_ptr,
                   const int32_t* col, const float* val, float alpha, float* grad, double* Z, double* kl, double* Zrow,
-                  hipStream_t s);
+                  hipStream_t s, const FusedStep* step = nullptr, hipEvent_t after_repulsion = nullptr);
 
 // Enqueue one optimiser step (arguments as tsne_step, validated).
 int step_launch(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr, float momentum,

@@ -2,8 +2,11 @@
 // per iteration one gradient evaluation (tsne_kl_grad's kernels) and one
 // step (tsne_step's kernel), with the schedule of van der Maaten & Hinton
 // 2008 (Sec. 3.4, Algorithm 1): early exaggeration and the lower momentum
-// while t < exaggeration_iters.  Same kernels and arithmetic as the separate
-// calls, so results are bitwise identical to calling them in a loop.
+// while t < exaggeration_iters.  The step is applied by the gradient's
+// finalize pass (one launch fewer per iteration); the embedding ping-pongs
+// between Y and a workspace copy, because that pass still gathers the old
+// positions of other rows while it writes new ones.  Same arithmetic as the
+// separate calls, so results are bitwise identical to calling them in a loop.
 #include "common.hpp"
 #include "klgrad.hpp"
 
@@ -20,11 +23,12 @@ extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, c
   const KlGradPlan L = klgrad_plan(n);
   Carve c;
   const size_t o_kg = c.take(L.bytes);
-  const size_t o_g = c.take(sizeof(float) * 2 * size_t(n));
+  const size_t o_y = c.take(sizeof(float) * 2 * size_t(n));
   int rc = workspace_protocol(workspace, workspace_bytes, c.off);
   if (rc >= 0) return rc;
   char* ws = static_cast<char*>(workspace);
-  float* grad = reinterpret_cast<float*>(ws + o_g);
+  float* ycur = Y;
+  float* ynext = reinterpret_cast<float*>(ws + o_y);
   hipStream_t s = as_stream(stream);
   for (int32_t t = t_begin; t < t_end; ++t) {
     const bool early = t < sc.exaggeration_iters;
@@ -36,15 +40,19 @@ extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, c
       const hipError_t e = hipEventRecord(static_cast<hipEvent_t>(events[2 * slot]), s);
       if (e != hipSuccess) { set_last_hip_error(e); return TSNE_ERR_HIP; }
     }
-    rc = klgrad_launch(L, ws + o_kg, Y, n, row_ptr, col, val, alpha, grad, nullptr, log ? kl_log + slot : nullptr,
-                       nullptr, s);
+    const FusedStep st{reinterpret_cast<float2*>(ynext), reinterpret_cast<float2*>(update),
+                       reinterpret_cast<float2*>(gains), sc.lr, mom, sc.gain_inc, sc.gain_dec, sc.min_gain};
+    rc = klgrad_launch(L, ws + o_kg, ycur, n, row_ptr, col, val, alpha, nullptr, nullptr,
+                       log ? kl_log + slot : nullptr, nullptr, s, &st,
+                       events ? static_cast<hipEvent_t>(events[2 * slot + 1]) : nullptr);
     if (rc) return rc;
-    if (events && events[2 * slot + 1]) {
-      const hipError_t e = hipEventRecord(static_cast<hipEvent_t>(events[2 * slot + 1]), s);
-      if (e != hipSuccess) { set_last_hip_error(e); return TSNE_ERR_HIP; }
-    }
-    rc = step_launch(Y, update, gains, grad, n, sc.lr, mom, sc.gain_inc, sc.gain_dec, sc.min_gain, s);
-    if (rc) return rc;
+    float* tmp = ycur;
+    ycur = ynext;
+    ynext = tmp;
+  }
+  if (ycur != Y) {
+    const hipError_t e = hipMemcpyAsync(Y, ycur, sizeof(float) * 2 * size_t(n), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) { set_last_hip_error(e); return TSNE_ERR_HIP; }
   }
   return TSNE_OK;
 }

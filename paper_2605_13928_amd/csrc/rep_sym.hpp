@@ -4,21 +4,26 @@
 //   R_i += w^2 (y_i - y_j),  R_j -= w^2 (y_i - y_j),  Z += 2 w.
 // That halves the reciprocals and differences of the ordered-pair sweep.
 //
-// Decomposition.  Points are cut into superblocks of S (a multiple of 64);
-// a workgroup of 4 waves owns one superblock pair (s, t), s <= t.  A wave
-// tile is 64 i-points x 64 j-points on an 8 x 8 lane grid: lane (a, b)
-// = lane (8a + b) holds i-points 8a..8a+7 and j-points 8b..8b+7 in
-// registers and evaluates their 64 pairs with no data movement.  Each wave
-// sweeps its i-subblocks (64 points of s, round robin over the 4 waves)
-// across the j-tiles of t (staged in LDS): i-side sums stay in registers;
-// after every tile the j-side sums are reduce-scattered over the 8 lanes
-// that share a j-group (gfx950 v_permlane32_swap / v_permlane16_swap, then
-// a DPP row rotation) and added to the wave's own LDS accumulator.  At the
-// end the workgroup adds the 4 wave accumulators in a fixed order and
-// writes one partial per point and opposite superblock: part[t][i] for
-// i in s and part[s][j] for j in t (for s == t both sides land in the same
-// slot and are added first).  A later pass sums the ns partials of a row in
-// index order, so the result is deterministic.
+// Decomposition.  Points are cut into superblocks of S (a multiple of 256);
+// a job is one superblock pair (s, t), s <= t, off-diagonal pairs first.  A
+// persistent grid of P workgroups takes jobs round robin (job q goes to
+// workgroup q mod P), so each workgroup's job list, and with it every sum,
+// is fixed; while it computes one job it already loads the points of its
+// next one into registers.  A workgroup has 4 waves; a wave tile is 64
+// i-points x 64 j-points on an 8 x 8 lane grid: lane (a, b) = lane (8a + b)
+// holds i-points 8a..8a+7 and j-points 8b..8b+7 in registers and evaluates
+// their 64 pairs with no data movement.  Each wave sweeps its i-subblocks
+// (64 points of s, round robin over the 4 waves) across the j-tiles of t
+// (both staged in LDS): i-side sums stay in registers; after every tile the
+// j-side sums are reduce-scattered over the 8 lanes that share a j-group
+// (gfx950 v_permlane32_swap / v_permlane16_swap, then a DPP row rotation)
+// and added to the wave's own LDS accumulator.  At the end of a job the
+// workgroup adds the 4 wave accumulators in a fixed order and writes one
+// partial per point and opposite superblock: part[t][i] for i in s and
+// part[s][j] for j in t (for s == t both sides land in the same slot and
+// are added first).  A later pass sums the ns partials of a row in index
+// order, and the P per-workgroup Z sums in index order, so the result is
+// deterministic.
 // In the diagonal superblock, tiles below the diagonal are skipped and the
 // 64 x 64 diagonal tiles take every ordered pair on the i side only, with
 // the self pair masked.  Points past n are placed far away,
@@ -117,35 +122,43 @@ __device__ __forceinline__ float2 load_point(const float2* __restrict__ Y, int64
   return make_float2(1e30f, 1e25f * float(p - n + 1));
 }
 
-#ifndef TSNE_SYM_MIN_WG
-#define TSNE_SYM_MIN_WG 1024
-#endif
+// Persistent grid: two workgroups per CU (the kernel's register use allows
+// two waves per SIMD) on the 256 CUs of an MI355X.
+constexpr int64_t SYM_GRID = 512;
+constexpr int SYM_MAX_S = 1024;
 
 struct SymGrid {
-  int64_t S, ns, nwg;
+  int64_t S, ns, njobs, nwg;
   static SymGrid make(int64_t n) {
     SymGrid g;
-    // largest S in {1024, 512, 256, 128, 64} that still gives enough workgroups
-    int64_t S = 1024;
-    while (S > 64) {
+    // largest S in {1024, 512, 256} that still gives each workgroup >= 4 jobs
+    int64_t S = SYM_MAX_S;
+    while (S > 256) {
       const int64_t ns = ceil_div(n, S);
-      if (ns * (ns + 1) / 2 >= TSNE_SYM_MIN_WG) break;
+      if (ns * (ns + 1) / 2 >= 4 * SYM_GRID) break;
       S >>= 1;
     }
     g.S = S;
     g.ns = ceil_div(n, S);
-    g.nwg = g.ns * (g.ns + 1) / 2;
+    g.njobs = g.ns * (g.ns + 1) / 2;
+    g.nwg = g.njobs < SYM_GRID ? g.njobs : SYM_GRID;
     return g;
   }
 };
 
-// Workgroup id -> (s, t), s <= t, row-major over t.
-__device__ __forceinline__ void wg_pair(int64_t g, int64_t& s, int64_t& t) {
-  int64_t tt = int64_t((sqrt(8.0 * double(g) + 1.0) - 1.0) * 0.5);
-  while ((tt + 1) * (tt + 2) / 2 <= g) ++tt;
-  while (tt * (tt + 1) / 2 > g) --tt;
+// Job q -> superblock pair (s, t): the ns (ns - 1) / 2 pairs s < t in
+// row-major order over t, then the ns diagonal pairs.
+__device__ __forceinline__ void job_pair(int64_t q, int64_t ns, int64_t& s, int64_t& t) {
+  const int64_t noff = ns * (ns - 1) / 2;
+  if (q >= noff) {
+    s = t = q - noff;
+    return;
+  }
+  int64_t tt = int64_t((1.0 + sqrt(1.0 + 8.0 * double(q))) * 0.5);
+  while (tt * (tt - 1) / 2 > q) --tt;
+  while ((tt + 1) * tt / 2 <= q) ++tt;
   t = tt;
-  s = g - tt * (tt + 1) / 2;
+  s = q - tt * (tt - 1) / 2;
 }
 
 // One 64 x 64 wave tile.  DIAG: i and j blocks coincide; all ordered pairs
@@ -191,136 +204,175 @@ __device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)
   }
 }
 
-// LDS layout of a workgroup (floats): pts[2*S] | iacc[NC*S] | jacc[4][NC*S]
-// with NC = 2 (x, y) or 3 (x, y, Z_row), component-major per accumulator.
-template <bool ZROW>
-__global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__ Y, int64_t n, int S, int64_t ns,
+// LDS layout of a workgroup (floats): ipts[2*S] | jpts[2*S] | iacc[NC*S] |
+// jacc[4][NC*S] with NC = 2 (x, y) or 3 (x, y, Z_row), component-major per
+// accumulator.
+// PF = S / 256: points per thread and side.
+template <bool ZROW, int PF>
+__global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__ Y, int64_t n, int64_t ns,
                                                       float* __restrict__ part, float* __restrict__ zpart,
                                                       double* __restrict__ Zblock) {
   constexpr int NC = ZROW ? 3 : 2;
+  constexpr int S = 256 * PF;
   extern __shared__ __attribute__((aligned(16))) float lds[];
-  __shared__ double red[256];
-  float2* pts = reinterpret_cast<float2*>(lds);
-  float* iacc = lds + 2 * S;
+  __shared__ double red[4];
+  float2* ipts = reinterpret_cast<float2*>(lds);
+  float2* jpts = ipts + S;
+  float* iacc = lds + 4 * S;
   float* jacc = iacc + NC * S;
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int a = lane >> 3, b = lane & 7;
-  int64_t s, t;
-  wg_pair(blockIdx.x, s, t);
-  const bool diag_sb = s == t;
-  const int64_t i0 = s * S, j0 = t * S;
   const int nsub = S / 64;
+  const int64_t njobs = ns * (ns + 1) / 2;
+  const int64_t P = gridDim.x;
+  float* myj = jacc + w * NC * S;
 
-  for (int u = tid; u < S; u += 256) pts[u] = load_point(Y, j0 + u, n);
+  // points of job q into registers (thread tid holds points tid + 256 k)
+  float2 pi[PF], pj[PF];
+  auto fetch = [&](int64_t q) {
+    int64_t s, t;
+    job_pair(q, ns, s, t);
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int u = tid + 256 * k;
+      pi[k] = load_point(Y, s * S + u, n);
+      pj[k] = load_point(Y, t * S + u, n);
+    }
+  };
+
+  int64_t q = blockIdx.x;
+  if (q < njobs) fetch(q);
   for (int u = tid; u < NC * S; u += 256) iacc[u] = 0.0f;
   for (int u = tid; u < SYM_WAVES * NC * S; u += 256) jacc[u] = 0.0f;
-  __syncthreads();
-
-  float* myj = jacc + w * NC * S;
   double zsum = 0.0;
-  for (int us = w; us < nsub; us += SYM_WAVES) {
-    // this wave's i-subblock: points i0 + 64 us + 8a + r
-    float xi[8], yi[8];
+  for (; q < njobs; q += P) {
+    int64_t s, t;
+    job_pair(q, ns, s, t);
+    const bool diag_sb = s == t;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const float2 p = load_point(Y, i0 + 64 * us + 8 * a + r, n);
-      xi[r] = p.x;
-      yi[r] = p.y;
+    for (int k = 0; k < PF; ++k) {
+      const int u = tid + 256 * k;
+      ipts[u] = pi[k];
+      jpts[u] = pj[k];
     }
-    float rix[8], riy[8], zi[8];
-    // after each fold this lane owns component bit2 of points 8a + c0 and
-    // 8a + c0 + 1 (c0 = 4 bit1 + 2 bit0), and Z_row of point 8a + cz
-    double di[2] = {0.0, 0.0}, dz = 0.0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) rix[r] = riy[r] = zi[r] = 0.0f;
-    const int v0 = diag_sb ? us : 0;
-    int since_fold = 0;
-    for (int v = v0; v < nsub; ++v) {
-      float rj[16], zj[8];
-      float z = 0.0f;
-      const float2* pj = pts + 64 * v + 8 * b;
-      if (diag_sb && v == us) {
-        sym_tile<true, ZROW>(xi, yi, pj, rix, riy, zi, rj, zj, z, a == b);
-        zsum += double(z);
-      } else {
-        sym_tile<false, ZROW>(xi, yi, pj, rix, riy, zi, rj, zj, z, false);
-        zsum += 2.0 * double(z);
-        // j side: reduce over the 8 lanes of this j-group, add into LDS
-        float o0, o1;
-        rs16_hi(rj, o0, o1);
-        const int comp = lane >> 5;
-        const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
-        float2* dst = reinterpret_cast<float2*>(myj + comp * S + 64 * v + 8 * b + c0);
-        float2 cur = *dst;
-        cur.x += o0;
-        cur.y += o1;
-        *dst = cur;
-        if (ZROW) {
-          const float oz = rs8_hi(zj);
-          const int cz = 4 * ((lane >> 5) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 3) & 1);
-          myj[2 * S + 64 * v + 8 * b + cz] += oz;
-        }
-      }
-      // fold the i-side sums into FP64 every 8 tiles (after an 8-lane reduce)
-      if (++since_fold == 8 || v == nsub - 1) {
-        since_fold = 0;
-        float vi[16];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          vi[r] = rix[r];
-          vi[8 + r] = riy[r];
-          rix[r] = riy[r] = 0.0f;
-        }
-        float o0, o1;
-        rs16_lo(vi, o0, o1);
-        di[0] += double(o0);
-        di[1] += double(o1);
-        if (ZROW) {
-          const float oz = rs8_lo(zi);
-          dz += double(oz);
-#pragma unroll
-          for (int r = 0; r < 8; ++r) zi[r] = 0.0f;
-        }
-      }
-    }
-    // i side of this subblock -> LDS (each point owned by exactly one wave)
-    {
-      const int comp = (lane >> 2) & 1;
-      const int c0 = 2 * (lane & 1) + 4 * ((lane >> 1) & 1);
-      float* dst = iacc + comp * S + 64 * us + 8 * a + c0;
-      dst[0] = float(di[0]);
-      dst[1] = float(di[1]);
-      if (ZROW) {
-        const int cz = 4 * ((lane >> 2) & 1) + 2 * ((lane >> 1) & 1) + (lane & 1);
-        iacc[2 * S + 64 * us + 8 * a + cz] = float(dz);
-      }
-    }
-  }
-  __syncthreads();
+    __syncthreads();  // points staged, accumulators zeroed
+    if (q + P < njobs) fetch(q + P);  // lands while this job computes
 
-  // write the partials: part[t][i in s] and part[s][j in t]
-  for (int u = tid; u < S; u += 256) {
-    float jx = 0.0f, jy = 0.0f, jz = 0.0f;
+    for (int us = w; us < nsub; us += SYM_WAVES) {
+      // this wave's i-subblock us: points s S + 64 us + 8a + r
+      float xi[8], yi[8];
 #pragma unroll
-    for (int ww = 0; ww < SYM_WAVES; ++ww) {
-      jx += jacc[ww * NC * S + u];
-      jy += jacc[ww * NC * S + S + u];
-      if (ZROW) jz += jacc[ww * NC * S + 2 * S + u];
+      for (int r = 0; r < 8; r += 2) {
+        const float4 v = *reinterpret_cast<const float4*>(ipts + 64 * us + 8 * a + r);
+        xi[r] = v.x;
+        yi[r] = v.y;
+        xi[r + 1] = v.z;
+        yi[r + 1] = v.w;
+      }
+      float rix[8], riy[8], zi[8];
+      // after each fold this lane owns component bit2 of points 8a + c0 and
+      // 8a + c0 + 1 (c0 = 4 bit1 + 2 bit0), and Z_row of point 8a + cz
+      double di[2] = {0.0, 0.0}, dz = 0.0;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) rix[r] = riy[r] = zi[r] = 0.0f;
+      const int v0 = diag_sb ? us : 0;
+      int since_fold = 0;
+      for (int v = v0; v < nsub; ++v) {
+        float rj[16], zj[8];
+        float z = 0.0f;
+        const float2* pjt = jpts + 64 * v + 8 * b;
+        if (diag_sb && v == us) {
+          sym_tile<true, ZROW>(xi, yi, pjt, rix, riy, zi, rj, zj, z, a == b);
+          zsum += double(z);
+        } else {
+          sym_tile<false, ZROW>(xi, yi, pjt, rix, riy, zi, rj, zj, z, false);
+          zsum += 2.0 * double(z);
+          // j side: reduce over the 8 lanes of this j-group, add into LDS
+          float o0, o1;
+          rs16_hi(rj, o0, o1);
+          const int comp = lane >> 5;
+          const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
+          float2* dst = reinterpret_cast<float2*>(myj + comp * S + 64 * v + 8 * b + c0);
+          float2 cur = *dst;
+          cur.x += o0;
+          cur.y += o1;
+          *dst = cur;
+          if (ZROW) {
+            const float oz = rs8_hi(zj);
+            const int cz = 4 * ((lane >> 5) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 3) & 1);
+            myj[2 * S + 64 * v + 8 * b + cz] += oz;
+          }
+        }
+        // fold the i-side sums into FP64 every 8 tiles (after an 8-lane reduce)
+        if (++since_fold == 8 || v == nsub - 1) {
+          since_fold = 0;
+          float vi[16];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            vi[r] = rix[r];
+            vi[8 + r] = riy[r];
+            rix[r] = riy[r] = 0.0f;
+          }
+          float o0, o1;
+          rs16_lo(vi, o0, o1);
+          di[0] += double(o0);
+          di[1] += double(o1);
+          if (ZROW) {
+            const float oz = rs8_lo(zi);
+            dz += double(oz);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) zi[r] = 0.0f;
+          }
+        }
+      }
+      // i side of this subblock -> LDS (each point owned by exactly one wave)
+      {
+        const int comp = (lane >> 2) & 1;
+        const int c0 = 2 * (lane & 1) + 4 * ((lane >> 1) & 1);
+        float* dst = iacc + comp * S + 64 * us + 8 * a + c0;
+        dst[0] = float(di[0]);
+        dst[1] = float(di[1]);
+        if (ZROW) {
+          const int cz = 4 * ((lane >> 2) & 1) + 2 * ((lane >> 1) & 1) + (lane & 1);
+          iacc[2 * S + 64 * us + 8 * a + cz] = float(dz);
+        }
+      }
     }
-    const int64_t pi = i0 + u, pj = j0 + u;
-    if (diag_sb) {
-      if (pi < n) {
-        reinterpret_cast<float2*>(part)[t * n + pi] = make_float2(iacc[u] - jx, iacc[S + u] - jy);
-        if (ZROW) zpart[t * n + pi] = iacc[2 * S + u] + jz;
+    __syncthreads();  // job's accumulators complete; staged points free
+
+    // write the partials part[t][i in s] and part[s][j in t]; each thread
+    // clears the accumulator entries it read, for the next job
+    const int64_t i0 = s * S, j0 = t * S;
+    for (int u = tid; u < S; u += 256) {
+      float jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+      for (int ww = 0; ww < SYM_WAVES; ++ww) {
+        jx += jacc[ww * NC * S + u];
+        jy += jacc[ww * NC * S + S + u];
+        if (ZROW) jz += jacc[ww * NC * S + 2 * S + u];
+        jacc[ww * NC * S + u] = 0.0f;
+        jacc[ww * NC * S + S + u] = 0.0f;
+        if (ZROW) jacc[ww * NC * S + 2 * S + u] = 0.0f;
       }
-    } else {
-      if (pi < n) {
-        reinterpret_cast<float2*>(part)[t * n + pi] = make_float2(iacc[u], iacc[S + u]);
-        if (ZROW) zpart[t * n + pi] = iacc[2 * S + u];
-      }
-      if (pj < n) {
-        reinterpret_cast<float2*>(part)[s * n + pj] = make_float2(-jx, -jy);
-        if (ZROW) zpart[s * n + pj] = jz;
+      const float ix = iacc[u], iy = iacc[S + u], iz = ZROW ? iacc[2 * S + u] : 0.0f;
+      iacc[u] = 0.0f;
+      iacc[S + u] = 0.0f;
+      if (ZROW) iacc[2 * S + u] = 0.0f;
+      const int64_t pi_ = i0 + u, pj_ = j0 + u;
+      if (diag_sb) {
+        if (pi_ < n) {
+          reinterpret_cast<float2*>(part)[t * n + pi_] = make_float2(ix - jx, iy - jy);
+          if (ZROW) zpart[t * n + pi_] = iz + jz;
+        }
+      } else {
+        if (pi_ < n) {
+          reinterpret_cast<float2*>(part)[t * n + pi_] = make_float2(ix, iy);
+          if (ZROW) zpart[t * n + pi_] = iz;
+        }
+        if (pj_ < n) {
+          reinterpret_cast<float2*>(part)[s * n + pj_] = make_float2(-jx, -jy);
+          if (ZROW) zpart[s * n + pj_] = jz;
+        }
       }
     }
   }
@@ -330,7 +382,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
 
 inline size_t rep_sym_lds_bytes(int64_t S, bool zrow) {
   const int nc = zrow ? 3 : 2;
-  return sizeof(float) * size_t(S) * size_t(2 + nc + SYM_WAVES * nc);
+  return sizeof(float) * size_t(S) * size_t(4 + nc + SYM_WAVES * nc);
 }
 
 }  // namespace tsne

@@ -6,15 +6,6 @@
 
 namespace tsne {
 
-__device__ __forceinline__ void step_coord(float& y, float& u, float& gain, float g, float lr, float mom, float inc,
-                                           float dec, float mn) {
-  float ng = (g * u < 0.0f) ? gain + inc : gain * dec;
-  ng = fmaxf(ng, mn);
-  u = mom * u - lr * ng * g;
-  y = y + u;
-  gain = ng;
-}
-
 __global__ __launch_bounds__(256) void step_kernel(float2* __restrict__ Y, float2* __restrict__ U,
                                                    float2* __restrict__ G, const float2* __restrict__ grad,
                                                    int64_t n, float lr, float mom, float inc, float dec, float mn) {

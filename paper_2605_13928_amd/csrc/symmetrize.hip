@@ -5,10 +5,11 @@
 //   1. in-degree histogram (integer atomics), exclusive scan -> in_ptr
 //   2. scatter (source, p) into the transposed lists (atomic cursors give an
 //      arbitrary order) ...
-//   3. ... which a per-row sort (one wave per row: register bitonic sort of
-//      (source, value) keys up to 1024 entries, a rank sort beyond) makes
-//      canonical
-//   4. rank-sort each row's k out-entries by column
+//   3. ... which a per-row sort makes canonical (one wave per row: register
+//      bitonic sort of (source, value) keys up to 1024 entries; one
+//      workgroup per longer row: LDS bitonic sort up to 8192, rank sort
+//      beyond)
+//   4. sort each row's k out-entries by column (wave bitonic sort)
 //   5. union size per row (binary search of each out-entry in the in-list),
 //      scan -> row_ptr
 //   6. merge by ranks: position of an element = its rank in its own list +
@@ -137,49 +138,10 @@ __global__ __launch_bounds__(256) void sym_scatter_kernel(const int32_t* __restr
   in_val[pos] = Pc[e];
 }
 
-// Stable rank sort of one segment per wave: element e goes to position
-// #{f : key_f < key_e} + #{f < e : key_f == key_e}, a permutation even when
-// keys repeat (repeats are reported through err).
-__device__ void wave_rank_sort_segment(const int32_t* __restrict__ key, const float* __restrict__ val, int64_t len,
-                                       int32_t* __restrict__ okey, float* __restrict__ oval, int* __restrict__ err) {
-  const int lane = lane_id();
-  for (int64_t b0 = 0; b0 < len; b0 += 256) {
-    int32_t mk[4];
-    int64_t rank[4];
-    bool own[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t e = b0 + lane + 64 * t;
-      own[t] = e < len;
-      mk[t] = own[t] ? key[e] : 0;
-      rank[t] = 0;
-    }
-    bool rep = false;
-    for (int64_t f = 0; f < len; ++f) {
-      const int32_t kf = key[f];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t e = b0 + lane + 64 * t;
-        const bool eq = kf == mk[t];
-        rank[t] += (kf < mk[t]) || (eq && f < e);
-        rep |= own[t] && eq && f != e;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (!own[t]) continue;
-      const int64_t e = b0 + lane + 64 * t;
-      okey[rank[t]] = mk[t];
-      oval[rank[t]] = val[e];
-    }
-    if (rep) atomicOr(err, 1);
-  }
-}
-
-// Bitonic variant for segments of at most EPL*64 entries: keys are
-// (source << 32 | value bits); sources in one in-list are distinct for valid
-// input, so the order is by source.  A repeated source (invalid input) is
-// reported through err.
+// Sort of one list of at most EPL*64 (index, value) entries by one wave
+// (register bitonic sort of index << 32 | value bits).  Indices in one list
+// are distinct for valid input, so the order is by index; a repeated index
+// (invalid input) is reported through err.
 template <int EPL>
 __device__ void wave_bitonic_segment(const int32_t* __restrict__ key, const float* __restrict__ val, int64_t len,
                                      int32_t* __restrict__ okey, float* __restrict__ oval, int* __restrict__ err) {
@@ -209,6 +171,11 @@ __device__ void wave_bitonic_segment(const int32_t* __restrict__ key, const floa
   if (rep) atomicOr(err, 1);
 }
 
+// In-lists up to WAVE_SORT_MAX entries: one wave per row, register bitonic
+// sort.  Longer lists (hubs of the kNN graph) are left to sym_sort_long_kernel.
+constexpr int64_t WAVE_SORT_MAX = 1024;
+constexpr int LDS_SORT_MAX = 8192;
+
 __global__ __launch_bounds__(256) void sym_sort_in_kernel(const int64_t* __restrict__ in_ptr,
                                                           const int32_t* __restrict__ in_src,
                                                           const float* __restrict__ in_val, int64_t n,
@@ -220,10 +187,102 @@ __global__ __launch_bounds__(256) void sym_sort_in_kernel(const int64_t* __restr
   const int64_t len = b - a;
   if (len <= 256)
     wave_bitonic_segment<4>(in_src + a, in_val + a, len, s_src + a, s_val + a, err);
-  else if (len <= 1024)
+  else if (len <= WAVE_SORT_MAX)
     wave_bitonic_segment<16>(in_src + a, in_val + a, len, s_src + a, s_val + a, err);
-  else
-    wave_rank_sort_segment(in_src + a, in_val + a, len, s_src + a, s_val + a, err);
+}
+
+// Long in-lists, one workgroup per list: bitonic sort of (source, value) keys
+// in LDS (padded to a power of two) up to LDS_SORT_MAX entries; beyond that a
+// stable rank sort with the keys streamed through LDS in tiles (quadratic,
+// for pathological hubs only).  Each block scans 256 rows and sorts those
+// with more than WAVE_SORT_MAX entries one after another.
+__device__ void block_bitonic_segment(uint64_t* keys, const int32_t* __restrict__ key, const float* __restrict__ val,
+                                      int64_t len, int32_t* __restrict__ okey, float* __restrict__ oval, bool& rep) {
+  const int tid = threadIdx.x;
+  int P = 1;
+  while (P < len) P <<= 1;
+  for (int e = tid; e < P; e += 256)
+    keys[e] = e < len ? ((uint64_t(uint32_t(key[e])) << 32) | __float_as_uint(val[e])) : KEY_MAX;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < P / 2; t += 256) {
+        const int i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));
+        const int j = i + stride;
+        const bool asc = (i & size) == 0;
+        const uint64_t x = keys[i], y = keys[j];
+        if ((x > y) == asc && x != y) {
+          keys[i] = y;
+          keys[j] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = tid; e < len; e += 256) {
+    const uint64_t v = keys[e];
+    const uint32_t hi = uint32_t(v >> 32);
+    if (e > 0 && uint32_t(keys[e - 1] >> 32) == hi) rep = true;
+    okey[e] = int32_t(hi);
+    oval[e] = __uint_as_float(uint32_t(v));
+  }
+}
+
+__device__ void block_rank_segment(int32_t* tile, const int32_t* __restrict__ key, const float* __restrict__ val,
+                                   int64_t len, int32_t* __restrict__ okey, float* __restrict__ oval, bool& rep) {
+  constexpr int TILE = 2 * LDS_SORT_MAX;  // int32 entries in the same LDS
+  const int tid = threadIdx.x;
+  for (int64_t c0 = 0; c0 < len; c0 += 256) {
+    const int64_t e = c0 + tid;
+    const bool own = e < len;
+    const int32_t mk = own ? key[e] : 0;
+    int64_t rank = 0;
+    for (int64_t f0 = 0; f0 < len; f0 += TILE) {
+      const int m = int(len - f0 < TILE ? len - f0 : TILE);
+      __syncthreads();
+      for (int u = tid; u < m; u += 256) tile[u] = key[f0 + u];
+      __syncthreads();
+      for (int u = 0; u < m; ++u) {
+        const int32_t kf = tile[u];
+        const int64_t f = f0 + u;
+        const bool eq = kf == mk;
+        rank += (kf < mk) || (eq && f < e);
+        rep |= own && eq && f != e;
+      }
+    }
+    if (own) {
+      okey[rank] = mk;
+      oval[rank] = val[e];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void sym_sort_long_kernel(const int64_t* __restrict__ in_ptr,
+                                                            const int32_t* __restrict__ in_src,
+                                                            const float* __restrict__ in_val, int64_t n,
+                                                            int32_t* __restrict__ s_src, float* __restrict__ s_val,
+                                                            int* __restrict__ err) {
+  extern __shared__ __attribute__((aligned(16))) uint64_t keys[];  // LDS_SORT_MAX entries
+  __shared__ int nlong;
+  __shared__ int64_t rows[256];
+  const int tid = threadIdx.x;
+  if (tid == 0) nlong = 0;
+  __syncthreads();
+  const int64_t row = int64_t(blockIdx.x) * 256 + tid;
+  if (row < n && in_ptr[row + 1] - in_ptr[row] > WAVE_SORT_MAX) rows[atomicAdd(&nlong, 1)] = row;
+  __syncthreads();
+  const int cnt = nlong;
+  bool rep = false;
+  for (int q = 0; q < cnt; ++q) {
+    const int64_t r = rows[q];
+    const int64_t a = in_ptr[r], len = in_ptr[r + 1] - a;
+    if (len <= LDS_SORT_MAX)
+      block_bitonic_segment(keys, in_src + a, in_val + a, len, s_src + a, s_val + a, rep);
+    else
+      block_rank_segment(reinterpret_cast<int32_t*>(keys), in_src + a, in_val + a, len, s_src + a, s_val + a, rep);
+    __syncthreads();
+  }
+  if (rep) atomicOr(err, 1);
 }
 
 __global__ __launch_bounds__(256) void sym_sort_out_kernel(const int32_t* __restrict__ nbr,
@@ -233,7 +292,7 @@ __global__ __launch_bounds__(256) void sym_sort_out_kernel(const int32_t* __rest
   const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const int64_t a = row * k;
-  wave_rank_sort_segment(nbr + a, Pc + a, k, o_col + a, o_val + a, err);
+  wave_bitonic_segment<TSNE_MAX_K / 64>(nbr + a, Pc + a, k, o_col + a, o_val + a, err);
 }
 
 // First position in sorted[0..len) whose value is >= x.
@@ -415,6 +474,9 @@ extern "C" int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int6
   hipLaunchKernelGGL(sym_scatter_kernel, g_edges, b, 0, s, nbr_idx, P_cond, n, k, in_ptr, cursor, in_src, in_val);
   TSNE_CHECK_LAUNCH();
   hipLaunchKernelGGL(sym_sort_in_kernel, g_rows, b, 0, s, in_ptr, in_src, in_val, n, s_src, s_val, err);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(sym_sort_long_kernel, dim3(unsigned(ceil_div(n, 256))), b, sizeof(uint64_t) * LDS_SORT_MAX, s,
+                     in_ptr, in_src, in_val, n, s_src, s_val, err);
   TSNE_CHECK_LAUNCH();
   hipLaunchKernelGGL(sym_sort_out_kernel, g_rows, b, 0, s, nbr_idx, P_cond, n, k, o_col, o_val, err);
   TSNE_CHECK_LAUNCH();

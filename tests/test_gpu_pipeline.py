@@ -83,7 +83,12 @@ def test_native_loop_equals_separate_calls(dev):
     assert sorted(a.kl) == sorted(b.kl) == [49, 99]
     for t in a.kl:
         assert a.kl[t].item() == b.kl[t].item()
-    # timing hook: one event pair per iteration, recorded around the gradient
+    # odd chunk lengths end with the embedding in the workspace copy (copied back)
+    c = tsne.iterate(tsne.iterate(tsne.State.start(Y0), A.P, w, 7), A.P, w, 6)
+    d = tsne.iterate_calls(tsne.State.start(Y0), A.P, w, 13)
+    assert c.t == d.t == 13
+    assert torch.equal(c.Y, d.Y) and torch.equal(c.update, d.update) and torch.equal(c.gains, d.gains)
+    # timing hook: one event pair per iteration, recorded around the repulsion kernel
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(20)]
     for e in evs:
         e.record()

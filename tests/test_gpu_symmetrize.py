@@ -44,29 +44,31 @@ def test_symmetrize_random_graphs(dev, n, k, seed):
     check(S, G, n)
 
 
-def test_symmetrize_hub_rows(dev):
-    # hubs with in-lists of ~300, ~900 and ~3000 entries exercise every
-    # per-row sort path (<= 256, <= 1024 and longer)
-    say("symmetrize hubs")
-    n, k = 3000, 20
+@pytest.mark.parametrize("n,k,hubs", [(3000, 20, {5: 300, 7: 900, 11: 2999}), (9000, 3, {0: 8999, 1: 5000})])
+def test_symmetrize_hub_rows(dev, n, k, hubs):
+    # hubs with in-lists of ~300, ~900, ~3000, ~5000 and ~9000 entries exercise
+    # every per-row sort path (wave: <= 256, <= 1024; workgroup: LDS bitonic
+    # <= 8192, rank sort beyond)
+    say("symmetrize hubs", n, k)
     rng = np.random.default_rng(9)
-    hubs = {5: 300, 7: 900, 11: n - 1}
     idx = np.empty((n, k), np.int32)
     for i in range(n):
-        row = [h for h, deg in hubs.items() if h != i and (deg == n - 1 or rng.random() < deg / n)]
-        pool = rng.permutation(n)
-        for j in pool:
-            if len(row) == k:
-                break
+        row = [h for h, deg in hubs.items() if h != i and (deg == n - 1 or rng.random() < deg / n)][:k]
+        while len(row) < k:
+            j = int(rng.integers(n))
             if j != i and j not in hubs and j not in row:
-                row.append(int(j))
+                row.append(j)
         idx[i] = row
     Pc = rng.random((n, k))
     Pc /= Pc.sum(1, keepdims=True)
     S, G = run_both(dev, idx, Pc)
     check(S, G, n)
     deg = np.diff(S.row_ptr)
-    assert deg[11] >= n - 1 and 200 < deg[5] < 400 and 700 < deg[7] < 1100
+    for h, d in hubs.items():
+        if d == n - 1:
+            assert deg[h] >= n - 1
+        else:
+            assert 0.7 * d < deg[h] < 1.3 * d
 
 
 def test_symmetrize_rejects_invalid_lists(dev):
