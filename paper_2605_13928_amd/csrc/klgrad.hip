@@ -11,19 +11,26 @@
 
 namespace tsne {
 
-// Finalize, 16 rows per block.  All loads that depend on nothing are
-// issued first (CSR bounds, the first repulsion partials, the Z partials,
-// the stepped rows' state), so the block's critical path is the three
-// dependent trips of the attraction gather (row_ptr -> col, val -> y_j).
+// Finalize, 16 rows per block.
+// Attraction A_i = sum_{e in row i} p_e w_e (y_i - y_j), entry-parallel: the
+// block's CSR entries are dealt to all 256 threads in chunks of FIN_CHUNK
+// (thread t takes entries c0 + t + 256 m, m < FIN_EPT), so a hub row with
+// thousands of entries costs the block no more dependent trips than a short
+// one: every thread issues its column/value loads, then its y_j gathers,
+// then writes p w (y_i - y_j) to LDS, and the 16 lanes of group g add row
+// g's contributions in entry order (strided by 16, then a DPP reduction).
+// Optional per-block sums of p ln p, p ln q (q = 1/w) and p for the KL.
 // Repulsion partials: thread (g, sl) adds slices g, g + 16, ... of row
-// r0 + sl in FP64; the 16 slice sums are combined in a fixed order.
-// Attraction A_i = sum_{e in row i} p_e w_e (y_i - y_j): lane group g owns
-// row r0 + g, 16 lanes, eight entries per lane in flight, reduced by DPP
-// row rotations; optional per-block sums of p ln p, p ln q (q = 1/w) and p
-// for the KL.  Then g_i = 4 (alpha A_i - R_i / Z).  STEP: instead of
-// storing g, apply the optimiser step to the row (FusedStep).
+// r0 + sl in FP64; the 16 slice sums are combined in a fixed order.  The
+// loads that depend on nothing (CSR bounds, the first partial slices, the Z
+// partials) are issued first.  Then
+// g_i = 4 (alpha A_i - R_i / Z); STEP: instead of storing g, apply the
+// optimiser step to the row (FusedStep).  Column indices outside [0, n)
+// contribute nothing.
 constexpr int FIN_ROWS = 16;
-constexpr int FIN_PRE = 8;  // partial slices per thread loaded up front
+constexpr int FIN_EPT = 8;
+constexpr int FIN_CHUNK = 256 * FIN_EPT;
+constexpr int FIN_PRE = 4;  // partial slices per thread loaded up front
 
 template <bool STEP>
 __global__ __launch_bounds__(256) void finalize_tsne_kernel(
@@ -31,30 +38,81 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     const float* __restrict__ val, float alpha, const float2* __restrict__ Rpart, const float* __restrict__ Zrowpart,
     int64_t ns, const double* __restrict__ Zblock, int64_t nZ, float2* __restrict__ grad, double* __restrict__ Zrow,
     double* __restrict__ Z_out, double* __restrict__ klpart, FusedStep st) {
+  __shared__ float2 contrib[FIN_CHUNK];
+  __shared__ int64_t rps[FIN_ROWS + 1];
+  __shared__ float2 yrow[FIN_ROWS];
   __shared__ double red[4];
   __shared__ double pr[16][FIN_ROWS][3];
   __shared__ float2 att[FIN_ROWS];
   const int tid = threadIdx.x;
   const int g = tid >> 4, sl = tid & 15;
   const int64_t r0 = int64_t(blockIdx.x) * FIN_ROWS;
-  const int64_t row = r0 + g;    // attraction row of lane group g
   const int64_t prow = r0 + sl;  // partial-sum row of this thread
 
   // --- loads with no dependences -----------------------------------------
-  int64_t e0 = 0, e1 = 0;
-  float2 yi = make_float2(0.0f, 0.0f);
-  if (row < n) {
-    e0 = row_ptr[row];
-    e1 = row_ptr[row + 1];
-    yi = Y[row];
-  }
-  float2 rp[FIN_PRE];
+  if (tid <= FIN_ROWS) rps[tid] = row_ptr[r0 + tid < n ? r0 + tid : n];
+  if (tid < FIN_ROWS) yrow[tid] = r0 + tid < n ? Y[r0 + tid] : make_float2(0.0f, 0.0f);
+  float2 rpv[FIN_PRE];
 #pragma unroll
   for (int u = 0; u < FIN_PRE; ++u) {
     const int64_t k = g + 16 * u;
-    rp[u] = (prow < n && k < ns) ? Rpart[k * n + prow] : make_float2(0.0f, 0.0f);
+    rpv[u] = (prow < n && k < ns) ? Rpart[k * n + prow] : make_float2(0.0f, 0.0f);
   }
   const double zt = zblock_thread_sum(Zblock, nZ);
+  __syncthreads();
+
+  // --- attraction, entry-parallel -----------------------------------------
+  const int64_t E0 = rps[0], E1 = rps[FIN_ROWS];
+  const int64_t ga = rps[g], gb = rps[g + 1];
+  float ax = 0.0f, ay = 0.0f, plp = 0.0f, plq = 0.0f, ps = 0.0f;
+  for (int64_t c0 = E0; c0 < E1; c0 += FIN_CHUNK) {
+    int32_t jj[FIN_EPT];
+    float pp[FIN_EPT];
+#pragma unroll
+    for (int m = 0; m < FIN_EPT; ++m) {
+      const int64_t e = c0 + tid + 256 * m;
+      const bool ok = e < E1;
+      jj[m] = ok ? col[e] : 0;
+      pp[m] = ok ? val[e] : 0.0f;
+    }
+#pragma unroll
+    for (int m = 0; m < FIN_EPT; ++m) {
+      if (jj[m] < 0 || jj[m] >= n) {
+        jj[m] = 0;
+        pp[m] = 0.0f;
+      }
+    }
+    float2 yj[FIN_EPT];
+#pragma unroll
+    for (int m = 0; m < FIN_EPT; ++m) yj[m] = Y[jj[m]];
+    int r = 0;  // row of the entry (entries of a thread are increasing)
+#pragma unroll
+    for (int m = 0; m < FIN_EPT; ++m) {
+      const int64_t e = c0 + tid + 256 * m;
+      while (r < FIN_ROWS - 1 && rps[r + 1] <= e) ++r;
+      const float2 yi = yrow[r];
+      const float dx = yi.x - yj[m].x, dy = yi.y - yj[m].y;
+      const float q = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f));
+      const float pw = pp[m] * __builtin_amdgcn_rcpf(q);
+      contrib[tid + 256 * m] = make_float2(pw * dx, pw * dy);
+      if (klpart) {
+        if (pp[m] > 0.0f) plp += pp[m] * logf(pp[m]);
+        plq += pp[m] * logf(q);
+        ps += pp[m];
+      }
+    }
+    __syncthreads();
+    const int64_t lo = ga > c0 ? ga : c0;
+    const int64_t hi = gb < c0 + FIN_CHUNK ? gb : c0 + FIN_CHUNK;
+    for (int64_t e = lo + sl; e < hi; e += 16) {
+      const float2 c = contrib[e - c0];
+      ax += c.x;
+      ay += c.y;
+    }
+    __syncthreads();
+  }
+
+  // the stepped rows' state (in flight while the partials are summed)
   float2 sy = make_float2(0.0f, 0.0f), su = sy, sg = sy;
   if (STEP && tid < FIN_ROWS && r0 + tid < n) {
     sy = Y[r0 + tid];
@@ -62,60 +120,30 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     sg = st.G[r0 + tid];
   }
 
-  // --- attraction --------------------------------------------------------
-  float ax = 0.0f, ay = 0.0f, plp = 0.0f, plq = 0.0f, ps = 0.0f;
-  for (int64_t e = e0 + sl; e < e1; e += 128) {
-    int32_t jj[8];
-    float pp[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t ee = e + 16 * u;
-      const bool ok = ee < e1;
-      jj[u] = ok ? col[ee] : int32_t(row);
-      pp[u] = ok ? val[ee] : 0.0f;
-    }
-    float2 yj[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) yj[u] = Y[jj[u]];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const float dx = yi.x - yj[u].x, dy = yi.y - yj[u].y;
-      const float q = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f));
-      const float pw = pp[u] * __builtin_amdgcn_rcpf(q);
-      ax = __builtin_fmaf(pw, dx, ax);
-      ay = __builtin_fmaf(pw, dy, ay);
-      if (klpart) {
-        if (pp[u] > 0.0f) plp += pp[u] * logf(pp[u]);
-        plq += pp[u] * logf(q);
-        ps += pp[u];
-      }
-    }
-  }
-
   // --- repulsion partials: slices g, g + 16, ... in order ------------------
   {
     double rx = 0.0, ry = 0.0, zr = 0.0;
 #pragma unroll
     for (int u = 0; u < FIN_PRE; ++u) {
-      rx += double(rp[u].x);
-      ry += double(rp[u].y);
+      rx += double(rpv[u].x);
+      ry += double(rpv[u].y);
     }
     if (prow < n) {
       int64_t k = g + 16 * FIN_PRE;
       for (; k + 48 < ns; k += 64) {
-        float2 r[4];
+        float2 rr[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = Rpart[(k + 16 * u) * n + prow];
+        for (int u = 0; u < 4; ++u) rr[u] = Rpart[(k + 16 * u) * n + prow];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          rx += double(r[u].x);
-          ry += double(r[u].y);
+          rx += double(rr[u].x);
+          ry += double(rr[u].y);
         }
       }
       for (; k < ns; k += 16) {
-        const float2 r = Rpart[k * n + prow];
-        rx += double(r.x);
-        ry += double(r.y);
+        const float2 rr = Rpart[k * n + prow];
+        rx += double(rr.x);
+        ry += double(rr.y);
       }
       if (Zrow)
         for (int64_t kk = g; kk < ns; kk += 16) zr += double(Zrowpart[kk * n + prow]);
@@ -153,13 +181,9 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     if (Zrow) Zrow[i] = Zr;
   }
   if (klpart) {
-    plp = row16_sum(plp);
-    plq = row16_sum(plq);
-    ps = row16_sum(ps);
-    const bool own = row < n && sl == 0;
-    const double a = block_sum_d(own ? double(plp) : 0.0, red);
-    const double b = block_sum_d(own ? double(plq) : 0.0, red);
-    const double c = block_sum_d(own ? double(ps) : 0.0, red);
+    const double a = block_sum_d(double(plp), red);
+    const double b = block_sum_d(double(plq), red);
+    const double c = block_sum_d(double(ps), red);
     if (tid == 0) {
       klpart[3 * blockIdx.x] = a;
       klpart[3 * blockIdx.x + 1] = b;

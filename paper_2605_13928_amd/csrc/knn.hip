@@ -8,12 +8,13 @@
 //            n_cand best per row kept, then re-ranked by FP32 direct
 //            differences on the original points.
 // Selection (both paths): every row owns a candidate buffer in global
-// memory, a count and a threshold tau in LDS.  A candidate with d <= tau is
-// appended (LDS atomic for the slot).  Before a buffer could overflow, the
-// owning wave sorts it (wave-wide bitonic sort of (d, j) keys), keeps the
-// best k and sets tau to the k-th distance.  The true k best always satisfy
-// d <= tau, so nothing is lost; ties at tau are kept and resolved by index
-// in the final sort.
+// memory; its count and threshold tau live in registers of the wave that
+// owns the row.  A candidate with d <= tau is appended; the slots of one
+// step's candidates come from ballots and popcounts (no atomics).  Before a
+// buffer could overflow, the owning wave sorts it (wave-wide bitonic sort of
+// (d, j) keys), keeps the best k and sets tau to the k-th distance.  The
+// true k best always satisfy d <= tau, so nothing is lost; ties at tau are
+// kept and resolved by index in the final sort.
 #include "common.hpp"
 
 namespace tsne {
@@ -26,11 +27,13 @@ namespace tsne {
 // write-back or invalidation beyond the CU.
 __device__ __forceinline__ void wg_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
+// Sort the c keys of a row's buffer, keep the best `keep`; returns the new
+// count and sets tau to the keep-th distance (infinity while c < keep).
+// Called by the whole wave with uniform arguments.
 template <int EPL>
-__device__ void compact_row(uint64_t* __restrict__ buf, int* cnt, float* tau, int keep) {
+__device__ int compact_row(uint64_t* __restrict__ buf, int c, int keep, float& tau) {
   const int lane = lane_id();
   wg_fence();  // earlier appends of this wave visible to the loads below
-  const int c = *cnt;
   uint64_t v[EPL];
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {
@@ -43,13 +46,9 @@ __device__ void compact_row(uint64_t* __restrict__ buf, int* cnt, float* tau, in
     const int e = t * 64 + lane;
     if (e < keep) buf[e] = v[t];
   }
-  float nt = INFINITY;
-  if (c >= keep) nt = key_dist(wave_pick<EPL>(v, keep - 1));
+  tau = c >= keep ? key_dist(wave_pick<EPL>(v, keep - 1)) : INFINITY;
   wg_fence();
-  if (lane == 0) {
-    *cnt = c < keep ? c : keep;
-    *tau = nt;
-  }
+  return c < keep ? c : keep;
 }
 
 // Sort a row's buffer and write its first `keep` keys out.
@@ -116,13 +115,16 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
   constexpr int CAP = 64 * EPL;
   __shared__ __attribute__((aligned(16))) float xi_s[F_DC * XI_S];
   __shared__ __attribute__((aligned(16))) float xj_s[F_DC * XJ_S];
-  __shared__ int cnt_s[F_ROWS];
-  __shared__ float tau_s[F_ROWS];
-  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t row0 = int64_t(blockIdx.x) * F_ROWS;
-  if (tid < F_ROWS) {
-    cnt_s[tid] = 0;
-    tau_s[tid] = row0 + tid < n ? INFINITY : -INFINITY;  // rows past n never accept
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  // per row of this wave (uniform): buffer count and threshold
+  int cnt[F_RW];
+  float tau[F_RW];
+#pragma unroll
+  for (int r = 0; r < F_RW; ++r) {
+    cnt[r] = 0;
+    tau[r] = row0 + w * F_RW + r < n ? INFINITY : -INFINITY;  // rows past n never accept
   }
   const bool one_chunk = d <= F_DC;
   if (one_chunk) stage_rows_t(xi_s, XI_S, X, row0, F_ROWS, n, d, 0, d);
@@ -153,45 +155,36 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
     // filter: one compare per candidate; the append path (and, only in the
     // tail step and the step holding the block's own rows, the index checks)
     // runs when some lane has a candidate at or below its row's threshold
-    float tau[F_RW];
     bool any = false;
 #pragma unroll
-    for (int r = 0; r < F_RW; ++r) {
-      tau[r] = tau_s[w * F_RW + r];
-      any |= (acc[r][0] <= tau[r]) | (acc[r][1] <= tau[r]);
-    }
+    for (int r = 0; r < F_RW; ++r) any |= (acc[r][0] <= tau[r]) | (acc[r][1] <= tau[r]);
     if (__ballot(any)) {
       const bool edge = (c0 + F_COLS > n) || (c0 < row0 + F_ROWS && row0 < c0 + F_COLS);
+      const int64_t j0 = c0 + lane * 2;
 #pragma unroll
       for (int r = 0; r < F_RW; ++r) {
-        const int lr = w * F_RW + r;
-        const int64_t gi = row0 + lr;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int64_t j = c0 + lane * 2 + u;
-          const float dd = acc[r][u];
-          if (dd <= tau[r] && (!edge || (j < n && j != gi))) {
-            const int pos = atomicAdd(&cnt_s[lr], 1);
-            bufs[gi * CAP + pos] = make_key(dd, int32_t(j));
-          }
-        }
+        const int64_t gi = row0 + w * F_RW + r;
+        const bool p0 = acc[r][0] <= tau[r] && (!edge || (j0 < n && j0 != gi));
+        const bool p1 = acc[r][1] <= tau[r] && (!edge || (j0 + 1 < n && j0 + 1 != gi));
+        const uint64_t m0 = __ballot(p0), m1 = __ballot(p1);
+        if ((m0 | m1) == 0) continue;
+        // slots in lane order, u = 0 before u = 1 within a lane
+        int pos = cnt[r] + __popcll(m0 & lt) + __popcll(m1 & lt);
+        uint64_t* buf = bufs + gi * CAP;
+        if (p0) buf[pos++] = make_key(acc[r][0], int32_t(j0));
+        if (p1) buf[pos] = make_key(acc[r][1], int32_t(j0 + 1));
+        cnt[r] += __popcll(m0) + __popcll(m1);
       }
       // compaction of rows that could overflow in the next step
-      const int cl = lane < F_RW ? cnt_s[w * F_RW + lane] : 0;
-      uint64_t need = __ballot(lane < F_RW && cl > CAP - F_COLS);
-      while (need) {
-        const int r = __ffsll((unsigned long long)need) - 1;
-        need &= need - 1;
-        const int lr = w * F_RW + r;
-        compact_row<EPL>(bufs + (row0 + lr) * CAP, &cnt_s[lr], &tau_s[lr], k);
-      }
+#pragma unroll
+      for (int r = 0; r < F_RW; ++r)
+        if (cnt[r] > CAP - F_COLS) cnt[r] = compact_row<EPL>(bufs + (row0 + w * F_RW + r) * CAP, cnt[r], k, tau[r]);
     }
   }
   for (int r = 0; r < F_RW; ++r) {
-    const int lr = w * F_RW + r;
-    const int64_t gi = row0 + lr;
+    const int64_t gi = row0 + w * F_RW + r;
     if (gi >= n) break;
-    emit_row<EPL>(bufs + gi * CAP, cnt_s[lr], k, out_idx + gi * k, out_d2 + gi * k);
+    emit_row<EPL>(bufs + gi * CAP, cnt[r], k, out_idx + gi * k, out_d2 + gi * k);
   }
 }
 
@@ -249,33 +242,43 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 constexpr int B_TJ = 64;  // candidates per LDS tile
 
+// LDS tile of B_TJ candidate rows, 8 chunks of 16 bytes each; chunk c of
+// row r is stored at r * 8 + (c ^ (r & 7)) so that 16 lanes reading chunk c
+// of 16 consecutive rows hit distinct banks.
+__device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r & 7)); }
+
+// Block = 4 waves x 64 queries.  Lane l works on queries 16 t + (l % 16),
+// t = 0..3, of its wave and, per 16-candidate subtile, on candidates
+// 4 (l / 16) .. + 3 (the MFMA C layout).  A query's count and threshold are
+// held (identically) by its four lanes.
 template <int EPL>
 __global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
                                                        int64_t n, int ncand, uint64_t* __restrict__ bufs,
                                                        int32_t* __restrict__ cand) {
   constexpr int CAP = 64 * EPL;
   __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
-  __shared__ int cnt_s[256];
-  __shared__ float tau_s[256];
-  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q16 = lane & 15, g4 = lane >> 4;
   const int64_t qblock = int64_t(blockIdx.x) * 256;
   const int64_t qbase = qblock + w * 64;
-  cnt_s[tid] = 0;
-  tau_s[tid] = INFINITY;
-  // query fragments: tile t, k-step s; lane holds query qbase + 16 t + lane % 16,
-  // k elements 32 s + 8 (lane / 16) ... + 7
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  const uint64_t qmask = uint64_t(0x0001000100010001ull) << q16;  // the four lanes of query q16
+  // query fragments: tile t, k-step s; lane holds query qbase + 16 t + q16,
+  // k elements 32 s + 8 g4 ... + 7
   bf16x8_t bq[4][2];
   float tau[4];
+  int cnt[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int64_t qi = qbase + t * 16 + (lane & 15);
+    const int64_t qi = qbase + t * 16 + q16;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       uint4 v = make_uint4(0, 0, 0, 0);
-      if (qi < n) v = Xq[qi * 8 + s * 4 + (lane >> 4)];
+      if (qi < n) v = Xq[qi * 8 + s * 4 + g4];
       bq[t][s] = __builtin_bit_cast(bf16x8_t, v);
     }
     tau[t] = qi < n ? INFINITY : -INFINITY;  // queries past n never accept
+    cnt[t] = 0;
   }
   // prefetch tile 0
   uint4 nxt[2];
@@ -288,7 +291,10 @@ __global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__
   int buf = 0;
   for (int64_t c0 = 0; c0 < n; c0 += B_TJ) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) tile[buf][tid + 256 * h] = nxt[h];
+    for (int h = 0; h < 2; ++h) {
+      const int u = tid + 256 * h;
+      tile[buf][tile_slot(u >> 3, u & 7)] = nxt[h];
+    }
     __syncthreads();
     // fetch the next tile while this one is consumed
     if (c0 + B_TJ < n) {
@@ -303,9 +309,9 @@ __global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__
     const bool edge = (c0 + B_TJ > n) || (c0 < qblock + 256 && qblock < c0 + B_TJ);
 #pragma unroll
     for (int sub = 0; sub < B_TJ / 16; ++sub) {
-      const int rloc = sub * 16 + (lane & 15);
-      const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, tl[rloc * 8 + (lane >> 4)]);
-      const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, tl[rloc * 8 + 4 + (lane >> 4)]);
+      const int rloc = sub * 16 + q16;
+      const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, tl[tile_slot(rloc, g4)]);
+      const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, tl[tile_slot(rloc, 4 + g4)]);
       floatx4_t acc[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -313,50 +319,68 @@ __global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bq[t][0], acc[t], 0, 0, 0);
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bq[t][1], acc[t], 0, 0, 0);
       }
-      // acc[t][r] = distance(query qbase + 16 t + lane % 16, candidate c0 + 16 sub + 4 (lane / 16) + r)
+      // acc[t][r] = distance(query qbase + 16 t + q16, candidate c0 + 16 sub + 4 g4 + r)
       bool any = false;
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) any |= acc[t][r] <= tau[t];
       if (__ballot(any)) {
+        const int64_t jb = c0 + sub * 16 + 4 * g4;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const int64_t qi = qbase + t * 16 + (lane & 15);
+          const int64_t qi = qbase + t * 16 + q16;
+          bool p[4];
+          uint64_t m[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int64_t j = c0 + sub * 16 + 4 * (lane >> 4) + r;
-            const float dd = acc[t][r];
-            if (dd <= tau[t] && (!edge || (j < n && j != qi))) {
-              const int lq = w * 64 + t * 16 + (lane & 15);
-              const int pos = atomicAdd(&cnt_s[lq], 1);
-              bufs[qi * CAP + pos] = make_key(fmaxf(dd, 0.0f), int32_t(j));
-            }
+            p[r] = acc[t][r] <= tau[t] && (!edge || (jb + r < n && jb + r != qi));
+            m[r] = __ballot(p[r]);
           }
+          if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
+          // slots of query qi: its lanes in lane order, r in order within a lane
+          int before = 0, total = 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            before += __popcll(m[r] & qmask & lt);
+            total += __popcll(m[r] & qmask);
+          }
+          int pos = cnt[t] + before;
+          uint64_t* bq_buf = bufs + qi * CAP;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (p[r]) bq_buf[pos++] = make_key(fmaxf(acc[t][r], 0.0f), int32_t(jb + r));
+          cnt[t] += total;
         }
       }
     }
-    const int cl = cnt_s[w * 64 + lane];
-    uint64_t need = __ballot(cl > CAP - B_TJ);
-    if (need) {
-      while (need) {
-        const int r = __ffsll((unsigned long long)need) - 1;
-        need &= need - 1;
-        const int lq = w * 64 + r;
-        compact_row<EPL>(bufs + (qbase + r) * CAP, &cnt_s[lq], &tau_s[lq], ncand);
-      }
+    // compaction of queries that could overflow in the next tile; lanes
+    // 0..15 speak for queries 16 t + lane
+    uint64_t need = 0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t qi = qbase + t * 16 + (lane & 15);
-        tau[t] = qi < n ? tau_s[w * 64 + t * 16 + (lane & 15)] : -INFINITY;
-      }
+    for (int t = 0; t < 4; ++t) need |= (__ballot(cnt[t] > CAP - B_TJ) & 0xFFFFull) << (16 * t);
+    while (need) {
+      const int r = __ffsll((unsigned long long)need) - 1;
+      need &= need - 1;
+      const int t = r >> 4, q = r & 15;
+      const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], q);
+      float nt;
+      const int nc = compact_row<EPL>(bufs + (qbase + r) * CAP, c, ncand, nt);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt)
+        if (tt == t && q16 == q) {
+          cnt[tt] = nc;
+          tau[tt] = nt;
+        }
     }
     buf ^= 1;
   }
   for (int r = 0; r < 64; ++r) {
     const int64_t qi = qbase + r;
     if (qi >= n) break;
-    emit_row<EPL>(bufs + qi * CAP, cnt_s[w * 64 + r], ncand, cand + qi * ncand, nullptr);
+    const int t = r >> 4;
+    const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], r & 15);
+    emit_row<EPL>(bufs + qi * CAP, c, ncand, cand + qi * ncand, nullptr);
   }
 }
 
