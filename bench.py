@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--iters", type=int, default=None, help="override the schedule's iteration count")
     ap.add_argument("--knn-compare-n", type=int, default=200_000,
                     help="point count of the BF16-vs-FP32 kNN build comparison (C3 shape)")
+    ap.add_argument("--autograd-n", type=int, default=50_000,
+                    help="point count of the KL autograd forward/backward timing (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -76,6 +78,10 @@ def traffic_from_profile(digest):
         return float(vals["hbm_bytes_per_call"])
     except (KeyError, ValueError):
         return None
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -130,6 +136,7 @@ def main():
     for _ in range(args.warmup):
         one_step(None)
     torch.cuda.synchronize()
+    progress(f"{args.warmup} warmup step(s) done")
 
     # two events per iteration per timed step, created (recorded once) up front
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * iters)] for _ in range(args.steps)]
@@ -144,6 +151,7 @@ def main():
         knn_ev.append(kev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    progress(f"{args.steps} timed step(s): {elapsed:.3f} s")
 
     pairs_per_step = float(n) * float(n - 1) * iters
     value = pairs_per_step * args.steps / elapsed
@@ -208,6 +216,43 @@ def main():
                    "bf16_vs_fp32_P_max_rel_common": float(rel.max()) if rel.nnz else 0.0,
                    "bf16_mfma_tflops_executed": mfma_flops / t16 / 1e12}
         del Xc, i32, d32, i16, d16, P32, P16, diff, both, rel
+        progress(f"kNN comparison at n={ncmp} done")
+
+    # --- differentiation form (KL autograd) at the 50k-point shape ----------
+    diff = {}
+    if args.autograd_n:
+        from paper_2605_13928_amd.autograd import kl_divergence
+
+        wd = synth.WORKLOADS["c4"]
+        nd = args.autograd_n
+        Xd = torch.from_numpy(synth.make_points(wd, n=nd)[0]).to(dev)
+        wsd = api.Workspace()
+        idd, d2d = api.knn(Xd, wd.k, "fp32", ws=wsd)
+        Pd = api.symmetrize(idd, api.calibrate_P(d2d, wd.perplexity)[0], want_tpos=True, ws=wsd)
+        Yd = torch.from_numpy(synth.make_init(wd, n=nd)).to(dev).requires_grad_(True)
+        vd = Pd.val.clone().requires_grad_(True)
+        fw, bw = [], []
+        for r in range(6):
+            Yd.grad = None
+            vd.grad = None
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            c = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            C = kl_divergence(Yd, vd, Pd)
+            b.record(stream)
+            C.backward()
+            c.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                fw.append(a.elapsed_time(b))
+                bw.append(b.elapsed_time(c))
+        pairs_d = float(nd) * (nd - 1)
+        diff = {"n": nd, "nnz": int(Pd.nnz), "forward_ms": float(np.median(fw)), "backward_ms": float(np.median(bw)),
+                "forward_pairs_per_s": pairs_d / (np.median(fw) * 1e-3),
+                "backward_pairs_per_s": pairs_d / (np.median(bw) * 1e-3), "KL": float(C.item())}
+        del Xd, Yd, vd, Pd, idd, d2d
+        progress(f"autograd timing at n={nd} done")
 
     # --- CPU baseline: the FP64 oracle on a bounded sample ------------------
     cpu = None
@@ -258,6 +303,7 @@ def main():
             t_it = (time.perf_counter() - t0) / args.cpu_iters
             it_desc = f"{args.cpu_iters} of {iters} gradient+step iterations (time x{iters / args.cpu_iters:g})"
         t_total = t_knn + t_ps + t_it * iters
+        progress("CPU baseline timed")
         cpu = {"value": pairs_per_step / t_total, "unit": "pair interactions/s", "cores": thr, "kind": "oracle",
                "sample": (f"FP64 oracle, {thr} threads: exact kNN on {qrows.size} of {n} query rows (time x"
                           f"{n / qrows.size:g}); calibration + symmetrisation of a full-size seeded k={w.k} graph; "
@@ -309,6 +355,7 @@ def main():
         "iteration_ms": iter_ms,
         "iteration_pairs_per_s": float(n) * (n - 1) / (iter_ms * 1e-3),
         "knn_build_s": {f"{w.knn}_in_step": knn_fp32_s, **knn_cmp},
+        "kl_autograd": diff,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "errors_vs_fp64": errors,

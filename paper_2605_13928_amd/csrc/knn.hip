@@ -11,10 +11,11 @@
 // memory; its count and threshold tau live in registers of the wave that
 // owns the row.  A candidate with d <= tau is appended; the slots of one
 // step's candidates come from ballots and popcounts (no atomics).  Before a
-// buffer could overflow, the owning wave sorts it (wave-wide bitonic sort of
-// (d, j) keys), keeps the best k and sets tau to the k-th distance.  The
-// true k best always satisfy d <= tau, so nothing is lost; ties at tau are
-// kept and resolved by index in the final sort.
+// buffer could overflow, the owning wave finds the k-th smallest distance
+// tau by a radix select, keeps the keys with d <= tau and makes tau the
+// new threshold.  The true k best always satisfy d <= tau, so nothing is
+// lost; ties at tau are kept and resolved by index in the final sort (a
+// wave-wide bitonic sort of the (d, j) keys).
 #include "common.hpp"
 
 namespace tsne {
@@ -27,12 +28,30 @@ namespace tsne {
 // write-back or invalidation beyond the CU.
 __device__ __forceinline__ void wg_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
-// Sort the c keys of a row's buffer, keep the best `keep`; returns the new
-// count and sets tau to the keep-th distance (infinity while c < keep).
-// Called by the whole wave with uniform arguments.
-template <int EPL>
-__device__ int compact_row(uint64_t* __restrict__ buf, int c, int keep, float& tau) {
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int x) {
   const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Shrink a row's buffer of c keys to the keys whose distance is at most the
+// keep-th smallest distance tau_d (all of the best `keep` by (d, j), plus
+// any further keys tied at tau_d), and set tau = tau_d.  tau_d is found by
+// a radix select on the distance bits (8 bits per pass, histograms in the
+// wave's 256-entry LDS array `hist`), so no sort is needed; the kept keys
+// are written in lane order.  If ties would leave more than `limit` keys,
+// the buffer is sorted instead and exactly `keep` are kept.  Returns the new
+// count.  Called by the whole wave with uniform arguments, c > keep.
+template <int EPL>
+__device__ int compact_row(uint64_t* __restrict__ buf, int c, int keep, int limit, float& tau,
+                           uint32_t* __restrict__ hist) {
+  const int lane = lane_id();
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
   wg_fence();  // earlier appends of this wave visible to the loads below
   uint64_t v[EPL];
 #pragma unroll
@@ -40,15 +59,73 @@ __device__ int compact_row(uint64_t* __restrict__ buf, int c, int keep, float& t
     const int e = t * 64 + lane;
     v[t] = e < c ? buf[e] : KEY_MAX;
   }
+  uint32_t prefix = 0, pmask = 0;
+  int k = keep, eq = 0;
+#pragma unroll
+  for (int shift = 24; shift >= 0; shift -= 8) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) hist[lane * 4 + u] = 0;
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) {
+      const uint32_t d = uint32_t(v[t] >> 32);
+      if (t * 64 + lane < c && (d & pmask) == prefix) atomicAdd(&hist[(d >> shift) & 255u], 1u);
+    }
+    uint32_t h[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) h[u] = hist[lane * 4 + u];
+    const int local = int(h[0] + h[1] + h[2] + h[3]);
+    const int incl = wave_incl_scan(local);
+    const int excl = incl - local;
+    const uint64_t owner = __ballot(excl < k && k <= incl);  // exactly one lane
+    const int L = __ffsll((unsigned long long)owner) - 1;
+    int run = excl, bin = lane * 4, hb = 0;
+    {
+      // first bin of this lane whose cumulative count reaches k
+      int acc = excl;
+      bool found = false;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!found && acc + int(h[u]) >= k) {
+          found = true;
+          bin = lane * 4 + u;
+          hb = int(h[u]);
+          run = acc;
+        }
+        acc += int(h[u]);
+      }
+    }
+    bin = __builtin_amdgcn_readlane(bin, L);
+    run = __builtin_amdgcn_readlane(run, L);
+    hb = __builtin_amdgcn_readlane(hb, L);
+    prefix |= uint32_t(bin) << shift;
+    pmask |= 0xFFu << shift;
+    k -= run;
+    eq = hb;
+  }
+  const int kept = (keep - k) + eq;  // keys with d < tau_d, plus those equal
+  if (kept <= limit) {
+    int base = 0;
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) {
+      const bool take = t * 64 + lane < c && uint32_t(v[t] >> 32) <= prefix;
+      const uint64_t m = __ballot(take);
+      if (take) buf[base + __popcll(m & lt)] = v[t];
+      base += __popcll(m);
+    }
+    tau = __uint_as_float(prefix);
+    wg_fence();
+    return kept;
+  }
+  // many keys tied at tau_d: sort and keep exactly `keep`
   wave_sort<EPL>(v);
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {
     const int e = t * 64 + lane;
     if (e < keep) buf[e] = v[t];
   }
-  tau = c >= keep ? key_dist(wave_pick<EPL>(v, keep - 1)) : INFINITY;
+  tau = key_dist(wave_pick<EPL>(v, keep - 1));
   wg_fence();
-  return c < keep ? c : keep;
+  return keep;
 }
 
 // Sort a row's buffer and write its first `keep` keys out.
@@ -82,7 +159,7 @@ __device__ void emit_row(const uint64_t* __restrict__ buf, int c, int keep, int3
 constexpr int F_RW = 16;
 constexpr int F_ROWS = 64;
 constexpr int F_COLS = 128;
-constexpr int F_DC = 64;
+constexpr int F_DC = 56;
 constexpr int XI_S = F_ROWS + 4;  // LDS row strides: multiples of 4 floats keep the
 constexpr int XJ_S = F_COLS + 4;  // 16-byte reads aligned and spread the stores' banks
 
@@ -115,6 +192,7 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
   constexpr int CAP = 64 * EPL;
   __shared__ __attribute__((aligned(16))) float xi_s[F_DC * XI_S];
   __shared__ __attribute__((aligned(16))) float xj_s[F_DC * XJ_S];
+  __shared__ uint32_t hist_s[4][256];  // per-wave radix-select histograms
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t row0 = int64_t(blockIdx.x) * F_ROWS;
   const uint64_t lt = (uint64_t(1) << lane) - 1;
@@ -178,7 +256,8 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
       // compaction of rows that could overflow in the next step
 #pragma unroll
       for (int r = 0; r < F_RW; ++r)
-        if (cnt[r] > CAP - F_COLS) cnt[r] = compact_row<EPL>(bufs + (row0 + w * F_RW + r) * CAP, cnt[r], k, tau[r]);
+        if (cnt[r] > CAP - F_COLS)
+          cnt[r] = compact_row<EPL>(bufs + (row0 + w * F_RW + r) * CAP, cnt[r], k, CAP - F_COLS, tau[r], hist_s[w]);
     }
   }
   for (int r = 0; r < F_RW; ++r) {
@@ -252,11 +331,12 @@ __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r 
 // 4 (l / 16) .. + 3 (the MFMA C layout).  A query's count and threshold are
 // held (identically) by its four lanes.
 template <int EPL>
-__global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
+__global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
                                                        int64_t n, int ncand, uint64_t* __restrict__ bufs,
                                                        int32_t* __restrict__ cand) {
   constexpr int CAP = 64 * EPL;
   __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
+  __shared__ uint32_t hist_s[4][256];   // per-wave radix-select histograms
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q16 = lane & 15, g4 = lane >> 4;
   const int64_t qblock = int64_t(blockIdx.x) * 256;
@@ -365,7 +445,7 @@ __global__ __launch_bounds__(256) void knn_bf16_kernel(const uint4* __restrict__
       const int t = r >> 4, q = r & 15;
       const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], q);
       float nt;
-      const int nc = compact_row<EPL>(bufs + (qbase + r) * CAP, c, ncand, nt);
+      const int nc = compact_row<EPL>(bufs + (qbase + r) * CAP, c, ncand, CAP - B_TJ, nt, hist_s[w]);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt)
         if (tt == t && q16 == q) {
