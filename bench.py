@@ -61,10 +61,11 @@ KLGRAD_SOURCES = ["paper_2605_13928_amd/csrc/klgrad.hip", "paper_2605_13928_amd/
                   "paper_2605_13928_amd/csrc/rep_sym.hpp", "paper_2605_13928_amd/csrc/common.hpp"]
 
 
-def traffic_from_profile(digest):
-    """HBM bytes per tsne_kl_grad call from the committed PMC summary, if it
-    was taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "kl_grad_c2_traffic.txt")
+def traffic_from_profile(digest, workload):
+    """HBM bytes per launch of the all-pairs kernel from the committed PMC
+    summary of this workload, if it was taken on the current kernel source;
+    else None."""
+    p = os.path.join(ROOT, "profiles", f"rep_sym_{workload}_traffic.txt")
     if not os.path.exists(p):
         return None
     vals = {}
@@ -162,7 +163,7 @@ def main():
     flops_per_call = api.KLGRAD_FLOPS_PER_ORDERED_PAIR * float(n) * float(n - 1)
     achieved_tflops = flops_per_call / (grad_ms_mean * 1e-3) / 1e12
     digest = source_digest(KLGRAD_SOURCES)
-    traffic = traffic_from_profile(digest)
+    traffic = traffic_from_profile(digest, args.workload)
 
     # --- BF16-MFMA vs FP32 kNN build, outside the timed region -------------
     knn_cmp = {}

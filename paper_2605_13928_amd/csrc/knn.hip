@@ -8,9 +8,9 @@
 //            n_cand best per row kept, then re-ranked by FP32 direct
 //            differences on the original points.
 // Selection (both paths): every row owns a candidate buffer in global
-// memory; its count and threshold tau live in registers of the wave that
-// owns the row.  A candidate with d <= tau is appended; the slots of one
-// step's candidates come from ballots and popcounts (no atomics).  Before a
+// memory, a count in LDS and a threshold tau in registers of the wave that
+// owns the row.  A candidate with d <= tau is appended; a lane reserves the
+// slots of all its candidates of one row and step with one LDS atomic.  Before a
 // buffer could overflow, the owning wave finds the k-th smallest distance
 // tau by a radix select, keeps the keys with d <= tau and makes tau the
 // new threshold.  The true k best always satisfy d <= tau, so nothing is
@@ -195,15 +195,12 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
   __shared__ uint32_t hist_s[4][256];  // per-wave radix-select histograms
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t row0 = int64_t(blockIdx.x) * F_ROWS;
-  const uint64_t lt = (uint64_t(1) << lane) - 1;
-  // per row of this wave (uniform): buffer count and threshold
-  int cnt[F_RW];
+  __shared__ int cnt_s[F_ROWS];  // buffer counts (appended by LDS atomics)
+  if (tid < F_ROWS) cnt_s[tid] = 0;  // published by the first staging barrier
+  // per row of this wave (uniform): threshold
   float tau[F_RW];
 #pragma unroll
-  for (int r = 0; r < F_RW; ++r) {
-    cnt[r] = 0;
-    tau[r] = row0 + w * F_RW + r < n ? INFINITY : -INFINITY;  // rows past n never accept
-  }
+  for (int r = 0; r < F_RW; ++r) tau[r] = row0 + w * F_RW + r < n ? INFINITY : -INFINITY;  // rows past n never accept
   const bool one_chunk = d <= F_DC;
   if (one_chunk) stage_rows_t(xi_s, XI_S, X, row0, F_ROWS, n, d, 0, d);
   for (int64_t c0 = 0; c0 < n; c0 += F_COLS) {
@@ -244,26 +241,34 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
         const int64_t gi = row0 + w * F_RW + r;
         const bool p0 = acc[r][0] <= tau[r] && (!edge || (j0 < n && j0 != gi));
         const bool p1 = acc[r][1] <= tau[r] && (!edge || (j0 + 1 < n && j0 + 1 != gi));
-        const uint64_t m0 = __ballot(p0), m1 = __ballot(p1);
-        if ((m0 | m1) == 0) continue;
-        // slots in lane order, u = 0 before u = 1 within a lane
-        int pos = cnt[r] + __popcll(m0 & lt) + __popcll(m1 & lt);
-        uint64_t* buf = bufs + gi * CAP;
-        if (p0) buf[pos++] = make_key(acc[r][0], int32_t(j0));
-        if (p1) buf[pos] = make_key(acc[r][1], int32_t(j0 + 1));
-        cnt[r] += __popcll(m0) + __popcll(m1);
+        const int c = int(p0) + int(p1);
+        if (c) {
+          int pos = atomicAdd(&cnt_s[w * F_RW + r], c);
+          uint64_t* buf = bufs + gi * CAP;
+          if (p0) buf[pos++] = make_key(acc[r][0], int32_t(j0));
+          if (p1) buf[pos] = make_key(acc[r][1], int32_t(j0 + 1));
+        }
       }
       // compaction of rows that could overflow in the next step
+      const int cl = cnt_s[w * F_RW + (lane & (F_RW - 1))];
+      uint64_t need = __ballot(lane < F_RW && cl > CAP - F_COLS);
+      while (need) {
+        const int r = __ffsll((unsigned long long)need) - 1;
+        need &= need - 1;
+        float nt;
+        const int nc = compact_row<EPL>(bufs + (row0 + w * F_RW + r) * CAP, __builtin_amdgcn_readlane(cl, r), k,
+                                        CAP - F_COLS, nt, hist_s[w]);
+        if (lane == 0) cnt_s[w * F_RW + r] = nc;
 #pragma unroll
-      for (int r = 0; r < F_RW; ++r)
-        if (cnt[r] > CAP - F_COLS)
-          cnt[r] = compact_row<EPL>(bufs + (row0 + w * F_RW + r) * CAP, cnt[r], k, CAP - F_COLS, tau[r], hist_s[w]);
+        for (int rr = 0; rr < F_RW; ++rr)
+          if (rr == r) tau[rr] = nt;
+      }
     }
   }
   for (int r = 0; r < F_RW; ++r) {
     const int64_t gi = row0 + w * F_RW + r;
     if (gi >= n) break;
-    emit_row<EPL>(bufs + gi * CAP, cnt[r], k, out_idx + gi * k, out_d2 + gi * k);
+    emit_row<EPL>(bufs + gi * CAP, cnt_s[w * F_RW + r], k, out_idx + gi * k, out_d2 + gi * k);
   }
 }
 
@@ -328,8 +333,8 @@ __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r 
 
 // Block = 4 waves x 64 queries.  Lane l works on queries 16 t + (l % 16),
 // t = 0..3, of its wave and, per 16-candidate subtile, on candidates
-// 4 (l / 16) .. + 3 (the MFMA C layout).  A query's count and threshold are
-// held (identically) by its four lanes.
+// 4 (l / 16) .. + 3 (the MFMA C layout).  A query's threshold is held
+// (identically) by its four lanes; its count is in LDS.
 template <int EPL>
 __global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
                                                        int64_t n, int ncand, uint64_t* __restrict__ bufs,
@@ -337,17 +342,16 @@ __global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restric
   constexpr int CAP = 64 * EPL;
   __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
   __shared__ uint32_t hist_s[4][256];   // per-wave radix-select histograms
+  __shared__ int cnt_s[256];            // buffer counts (appended by LDS atomics)
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q16 = lane & 15, g4 = lane >> 4;
   const int64_t qblock = int64_t(blockIdx.x) * 256;
   const int64_t qbase = qblock + w * 64;
-  const uint64_t lt = (uint64_t(1) << lane) - 1;
-  const uint64_t qmask = uint64_t(0x0001000100010001ull) << q16;  // the four lanes of query q16
+  cnt_s[tid] = 0;  // published by the first tile barrier
   // query fragments: tile t, k-step s; lane holds query qbase + 16 t + q16,
   // k elements 32 s + 8 g4 ... + 7
   bf16x8_t bq[4][2];
   float tau[4];
-  int cnt[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int64_t qi = qbase + t * 16 + q16;
@@ -358,7 +362,6 @@ __global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restric
       bq[t][s] = __builtin_bit_cast(bf16x8_t, v);
     }
     tau[t] = qi < n ? INFINITY : -INFINITY;  // queries past n never accept
-    cnt[t] = 0;
   }
   // prefetch tile 0
   uint4 nxt[2];
@@ -411,56 +414,43 @@ __global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restric
         for (int t = 0; t < 4; ++t) {
           const int64_t qi = qbase + t * 16 + q16;
           bool p[4];
-          uint64_t m[4];
+          int c = 0;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             p[r] = acc[t][r] <= tau[t] && (!edge || (jb + r < n && jb + r != qi));
-            m[r] = __ballot(p[r]);
+            c += int(p[r]);
           }
-          if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
-          // slots of query qi: its lanes in lane order, r in order within a lane
-          int before = 0, total = 0;
+          if (c) {
+            int pos = atomicAdd(&cnt_s[w * 64 + t * 16 + q16], c);
+            uint64_t* qbuf = bufs + qi * CAP;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            before += __popcll(m[r] & qmask & lt);
-            total += __popcll(m[r] & qmask);
+            for (int r = 0; r < 4; ++r)
+              if (p[r]) qbuf[pos++] = make_key(fmaxf(acc[t][r], 0.0f), int32_t(jb + r));
           }
-          int pos = cnt[t] + before;
-          uint64_t* bq_buf = bufs + qi * CAP;
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (p[r]) bq_buf[pos++] = make_key(fmaxf(acc[t][r], 0.0f), int32_t(jb + r));
-          cnt[t] += total;
         }
       }
     }
-    // compaction of queries that could overflow in the next tile; lanes
-    // 0..15 speak for queries 16 t + lane
-    uint64_t need = 0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) need |= (__ballot(cnt[t] > CAP - B_TJ) & 0xFFFFull) << (16 * t);
+    // compaction of queries that could overflow in the next tile (lane l
+    // speaks for query l of the wave)
+    const int cl = cnt_s[w * 64 + lane];
+    uint64_t need = __ballot(cl > CAP - B_TJ);
     while (need) {
       const int r = __ffsll((unsigned long long)need) - 1;
       need &= need - 1;
-      const int t = r >> 4, q = r & 15;
-      const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], q);
       float nt;
-      const int nc = compact_row<EPL>(bufs + (qbase + r) * CAP, c, ncand, CAP - B_TJ, nt, hist_s[w]);
+      const int nc = compact_row<EPL>(bufs + (qbase + r) * CAP, __builtin_amdgcn_readlane(cl, r), ncand, CAP - B_TJ,
+                                      nt, hist_s[w]);
+      if (lane == 0) cnt_s[w * 64 + r] = nc;
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
-        if (tt == t && q16 == q) {
-          cnt[tt] = nc;
-          tau[tt] = nt;
-        }
+      for (int t = 0; t < 4; ++t)
+        if (t == (r >> 4) && q16 == (r & 15)) tau[t] = nt;
     }
     buf ^= 1;
   }
   for (int r = 0; r < 64; ++r) {
     const int64_t qi = qbase + r;
     if (qi >= n) break;
-    const int t = r >> 4;
-    const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], r & 15);
-    emit_row<EPL>(bufs + qi * CAP, c, ncand, cand + qi * ncand, nullptr);
+    emit_row<EPL>(bufs + qi * CAP, cnt_s[w * 64 + r], ncand, cand + qi * ncand, nullptr);
   }
 }
 

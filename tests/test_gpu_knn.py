@@ -51,6 +51,31 @@ def test_knn_fp32_exact_ties(dev):
     check_knn(X, np.arange(X.shape[0]), gi, gd, oi, od)
 
 
+def test_knn_massive_ties(dev):
+    # 8 distinct points, each repeated 500 times in shuffled order: every
+    # query has 499 neighbours at distance 0, more than a candidate buffer
+    # can keep at its threshold, which takes the sort branch of the
+    # compaction.  FP32: the k smallest indices among the duplicates, as the
+    # oracle's (d, j) order gives.  BF16: which duplicates survive the
+    # candidate stage depends on BF16 rounding, so only validity is checked.
+    say("knn massive ties")
+    rng = np.random.default_rng(5)
+    base = (rng.standard_normal((8, 50)) * 5).astype(np.float32)
+    lab = rng.permutation(np.repeat(np.arange(8), 500))
+    X = base[lab]
+    k = 90
+    oi, od = oracle.knn(X, k)
+    gi, gd = gpu_knn(dev, X, k)
+    np.testing.assert_array_equal(gi, oi)
+    assert (gd == 0).all()
+    bi, bd = gpu_knn(dev, X, k, "bf16", n_cand=180)
+    n = X.shape[0]
+    assert (bd == 0).all()
+    assert (lab[bi] == lab[:, None]).all()
+    assert (bi != np.arange(n)[:, None]).all()
+    assert all(len(set(r)) == k for r in bi.tolist())
+
+
 def test_knn_fp32_c2_sampled_rows(dev):
     say("knn fp32 c2 full")
     X, _ = synth.make_points("c2")
