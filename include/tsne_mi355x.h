@@ -112,9 +112,14 @@ int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t precision,
  * s_j = d_ij - min_l d_il, p_{j|i} = exp(-beta_i s_j) / sum_l exp(-beta_i s_l),
  * with beta_i found by bisection (start 1, bracket (0, inf), doubling until
  * bracketed) so that the entropy H = ln sum_l e^{-beta s_l} + beta sum_j p_j s_j
- * equals ln(perplexity) nats to within tol.  Rows that do not reach it in
- * max_iter evaluations (e.g. all k distances equal) keep the last beta and
- * get converged = 0.
+ * equals ln(perplexity) nats to within tol.  H is evaluated in FP32 and the
+ * search stops once that evaluation is within tol - min(TSNE_CALIB_H_MARGIN,
+ * tol / 2): the margin covers the FP32 evaluation error of H (sums of k
+ * exponentials; a few 1e-7 at k = 90 against an FP64 evaluation), so the
+ * entropy at the returned beta, evaluated in FP64 from the same FP32
+ * distances, is within tol.
+ * Rows that do not reach it in max_iter evaluations (e.g. all k distances
+ * equal) keep the last beta and get converged = 0.
  *
  *   nbr_d2     [n][k] float, read-only (any order within a row).
  *   perplexity 0 < perplexity < k.   tol > 0.   max_iter >= 1.
@@ -122,6 +127,8 @@ int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t precision,
  *   beta       [n] float out (nullable).  converged [n] uint8 out (nullable).
  *   n_unconverged  device int32 scalar out (nullable): rows with converged 0.
  */
+#define TSNE_CALIB_H_MARGIN 2e-6f
+
 int tsne_calibrate_P(const float* nbr_d2, int64_t n, int32_t k, float perplexity, float tol, int32_t max_iter,
                      float* P_cond, float* beta, uint8_t* converged, int32_t* n_unconverged, void* stream);
 

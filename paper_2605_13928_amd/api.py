@@ -190,8 +190,8 @@ def optimize(Y, update, gains, P: SparseP, t_begin: int, t_end: int, lr: float =
 
     kl_log: float64 device tensor of t_end - t_begin entries (KL written at
     iterations with (t + 1) % log_every == 0).  events: optional list of
-    2 (t_end - t_begin) torch.cuda.Event (recorded around each launch of the
-    all-pairs repulsion kernel).
+    2 (t_end - t_begin) torch.cuda.Event or None (recorded around each launch
+    of the all-pairs repulsion kernel; None entries are skipped).
     """
     n = Y.shape[0]
     for t, name in ((Y, "Y"), (update, "update"), (gains, "gains")):
@@ -205,8 +205,8 @@ def optimize(Y, update, gains, P: SparseP, t_begin: int, t_end: int, lr: float =
     if events is not None:
         if len(events) != 2 * iters:
             raise ValueError("need two events per iteration")
-        handles = [int(e.cuda_event) for e in events]
-        if not all(handles):
+        handles = [0 if e is None else int(e.cuda_event) for e in events]
+        if not all(h for h, e in zip(handles, events) if e is not None):
             raise ValueError("events must have been created (record each once) before use")
         ev_arr = C.cast((C.c_void_p * (2 * iters))(*handles), C.c_void_p)
     sc = _lib.Schedule(lr, exaggeration, exaggeration_iters, momentum_early, momentum_late, gain_inc, gain_dec,

@@ -87,13 +87,16 @@ extern "C" int tsne_calibrate_P(const float* nbr_d2, int64_t n, int32_t k, float
     if (rc) return rc;
   }
   const float Hstar = logf(perplexity);
+  // the search compares an FP32 evaluation of H; stopping that much inside
+  // tol keeps the entropy at the returned beta within tol
+  const float tol_fp32 = tol - fminf(TSNE_CALIB_H_MARGIN, 0.5f * tol);
   dim3 grid(unsigned(ceil_div(n, 4))), block(256);
   const int kpl = int(ceil_div(k, 64));
   switch (kpl) {
-    case 1: hipLaunchKernelGGL(calibrate_kernel<1>, grid, block, 0, s, nbr_d2, n, k, Hstar, tol, max_iter, P_cond, beta, converged, n_unconverged); break;
-    case 2: hipLaunchKernelGGL(calibrate_kernel<2>, grid, block, 0, s, nbr_d2, n, k, Hstar, tol, max_iter, P_cond, beta, converged, n_unconverged); break;
-    case 3: hipLaunchKernelGGL(calibrate_kernel<3>, grid, block, 0, s, nbr_d2, n, k, Hstar, tol, max_iter, P_cond, beta, converged, n_unconverged); break;
-    default: hipLaunchKernelGGL(calibrate_kernel<4>, grid, block, 0, s, nbr_d2, n, k, Hstar, tol, max_iter, P_cond, beta, converged, n_unconverged); break;
+    case 1: hipLaunchKernelGGL(calibrate_kernel<1>, grid, block, 0, s, nbr_d2, n, k, Hstar, tol_fp32, max_iter, P_cond, beta, converged, n_unconverged); break;
+    case 2: hipLaunchKernelGGL(calibrate_kernel<2>, grid, block, 0, s, nbr_d2, n, k, Hstar, tol_fp32, max_iter, P_cond, beta, converged, n_unconverged); break;
+    case 3: hipLaunchKernelGGL(calibrate_kernel<3>, grid, block, 0, s, nbr_d2, n, k, Hstar, tol_fp32, max_iter, P_cond, beta, converged, n_unconverged); break;
+    default: hipLaunchKernelGGL(calibrate_kernel<4>, grid, block, 0, s, nbr_d2, n, k, Hstar, tol_fp32, max_iter, P_cond, beta, converged, n_unconverged); break;
   }
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;

@@ -36,8 +36,8 @@ template <bool STEP>
 __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     const float2* __restrict__ Y, int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, float alpha, const float2* __restrict__ Rpart, const float* __restrict__ Zrowpart,
-    int64_t ns, const double* __restrict__ Zblock, int64_t nZ, float2* __restrict__ grad, double* __restrict__ Zrow,
-    double* __restrict__ Z_out, double* __restrict__ klpart, FusedStep st) {
+    int64_t ns, bool grouped, const double* __restrict__ Zblock, int64_t nZ, float2* __restrict__ grad,
+    double* __restrict__ Zrow, double* __restrict__ Z_out, double* __restrict__ klpart, FusedStep st) {
   __shared__ float2 contrib[FIN_CHUNK];
   __shared__ int64_t rps[FIN_ROWS + 1];
   __shared__ float2 yrow[FIN_ROWS];
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
 #pragma unroll
   for (int u = 0; u < FIN_PRE; ++u) {
     const int64_t k = g + 16 * u;
-    rpv[u] = (prow < n && k < ns) ? Rpart[k * n + prow] : make_float2(0.0f, 0.0f);
+    rpv[u] = (prow < n && k < ns) ? Rpart[part_index(prow, k, ns, n, grouped)] : make_float2(0.0f, 0.0f);
   }
   const double zt = zblock_thread_sum(Zblock, nZ);
   __syncthreads();
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
       for (; k + 48 < ns; k += 64) {
         float2 rr[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) rr[u] = Rpart[(k + 16 * u) * n + prow];
+        for (int u = 0; u < 4; ++u) rr[u] = Rpart[part_index(prow, k + 16 * u, ns, n, grouped)];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           rx += double(rr[u].x);
@@ -141,12 +141,12 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
         }
       }
       for (; k < ns; k += 16) {
-        const float2 rr = Rpart[k * n + prow];
+        const float2 rr = Rpart[part_index(prow, k, ns, n, grouped)];
         rx += double(rr.x);
         ry += double(rr.y);
       }
       if (Zrow)
-        for (int64_t kk = g; kk < ns; kk += 16) zr += double(Zrowpart[kk * n + prow]);
+        for (int64_t kk = g; kk < ns; kk += 16) zr += double(Zrowpart[part_index(prow, kk, ns, n, grouped)]);
     }
     pr[g][sl][0] = rx;
     pr[g][sl][1] = ry;
@@ -215,8 +215,9 @@ KlGradPlan klgrad_plan(int64_t n) {
   L.g = SymGrid::make(n);
   L.nfin = ceil_div(n, FIN_ROWS);
   Carve c;
-  L.o_R = c.take(sizeof(float2) * size_t(L.g.ns) * size_t(n));
-  L.o_Zr = c.take(sizeof(float) * size_t(L.g.ns) * size_t(n));
+  const size_t n16 = size_t(ceil_div(n, 16)) * 16;
+  L.o_R = c.take(sizeof(float2) * size_t(L.g.ns) * n16);
+  L.o_Zr = c.take(sizeof(float) * size_t(L.g.ns) * n16);
   L.o_Zb = c.take(sizeof(double) * size_t(L.g.nwg));
   L.o_kl = c.take(sizeof(double) * 3 * size_t(L.nfin));
   L.bytes = c.off;
@@ -256,12 +257,12 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
   }
   if (step)
     hipLaunchKernelGGL(finalize_tsne_kernel<true>, dim3(unsigned(L.nfin)), dim3(256), 0, s, Y2, n, row_ptr, col, val,
-                       alpha, reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, Zblock, g.nwg, nullptr, Zrow, Z,
-                       klpart, *step);
+                       alpha, reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, part_grouped(g.S), Zblock,
+                       g.nwg, nullptr, Zrow, Z, klpart, *step);
   else
     hipLaunchKernelGGL(finalize_tsne_kernel<false>, dim3(unsigned(L.nfin)), dim3(256), 0, s, Y2, n, row_ptr, col,
-                       val, alpha, reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, Zblock, g.nwg,
-                       reinterpret_cast<float2*>(grad), Zrow, Z, klpart, FusedStep{});
+                       val, alpha, reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, part_grouped(g.S), Zblock,
+                       g.nwg, reinterpret_cast<float2*>(grad), Zrow, Z, klpart, FusedStep{});
   TSNE_CHECK_LAUNCH();
   if (kl) {
     hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, klpart, L.nfin, Zblock, g.nwg, kl);

@@ -19,9 +19,9 @@
 // (gfx950 v_permlane32_swap / v_permlane16_swap, then a DPP row rotation)
 // and added to the wave's own LDS accumulator.  At the end of a job the
 // workgroup adds the 4 wave accumulators in a fixed order and writes one
-// partial per point and opposite superblock: part[t][i] for i in s and
-// part[s][j] for j in t (for s == t both sides land in the same slot and
-// are added first).  A later pass sums the ns partials of a row in index
+// partial per point and opposite superblock: slice t for i in s and slice
+// s for j in t (for s == t both sides land in the same slot and are added
+// first).  A later pass sums the ns partials of a row in index
 // order, and the P per-workgroup Z sums in index order, so the result is
 // deterministic.
 // In the diagonal superblock, tiles below the diagonal are skipped and the
@@ -122,6 +122,20 @@ __device__ __forceinline__ float2 load_point(const float2* __restrict__ Y, int64
   return make_float2(1e30f, 1e25f * float(p - n + 1));
 }
 
+// Partial of point p for opposite superblock k.  Grouped layout (small
+// superblocks, where the finalize pass dominates): points are grouped by 16
+// and each group keeps its ns slices together (16 consecutive points per
+// slice), so the finalize pass reads one contiguous run per group of 16
+// rows while a job still writes whole 128-byte lines.  Slice-major layout
+// (large superblocks, where the partial writes dominate): slice k holds all
+// n points, so a job writes S consecutive points per side.  The buffer holds
+// ns * round_up(n, 16) entries either way.
+__device__ __forceinline__ int64_t part_index(int64_t p, int64_t k, int64_t ns, int64_t n, bool grouped) {
+  return grouped ? ((p >> 4) * ns + k) * 16 + (p & 15) : k * n + p;
+}
+// The layout that goes with superblock size S.
+__host__ __device__ constexpr bool part_grouped(int64_t S) { return S <= 256; }
+
 // Persistent grid: two workgroups per CU (the kernel's register use allows
 // two waves per SIMD) on the 256 CUs of an MI355X.
 constexpr int64_t SYM_GRID = 512;
@@ -164,13 +178,13 @@ __device__ __forceinline__ void job_pair(int64_t q, int64_t ns, int64_t& s, int6
 // One 64 x 64 wave tile.  DIAG: i and j blocks coincide; all ordered pairs
 // go to the i side, self pairs masked, Z weight 1 (else 2, via the caller).
 template <bool DIAG, bool ZROW>
-__device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)[8], const float2* __restrict__ pj,
+__device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)[8], const float4 (&pjv)[4],
                                          float (&rix)[8], float (&riy)[8], float (&zi)[8], float (&rj)[16],
                                          float (&zj)[8], float& z, bool same_group) {
   float xj[8], yj[8];
 #pragma unroll
   for (int c = 0; c < 8; c += 2) {
-    const float4 v = *reinterpret_cast<const float4*>(pj + c);
+    const float4 v = pjv[c / 2];
     xj[c] = v.x;
     yj[c] = v.y;
     xj[c + 1] = v.z;
@@ -223,6 +237,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int a = lane >> 3, b = lane & 7;
   const int nsub = S / 64;
+  constexpr bool JPF = PF == 1;
   const int64_t njobs = ns * (ns + 1) / 2;
   const int64_t P = gridDim.x;
   float* myj = jacc + w * NC * S;
@@ -277,23 +292,39 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       for (int r = 0; r < 8; ++r) rix[r] = riy[r] = zi[r] = 0.0f;
       const int v0 = diag_sb ? us : 0;
       int since_fold = 0;
+      // j-points of the next tile are read from LDS while this one computes
+      // (when the registers allow it: JPF)
+      float4 jn[4];
+      auto load_j = [&](int v) {
+        const float4* p = reinterpret_cast<const float4*>(jpts + 64 * v + 8 * b);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) jn[c] = p[c];
+      };
+      if (JPF) load_j(v0);
+      const int comp = lane >> 5;
+      const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
       for (int v = v0; v < nsub; ++v) {
+        float4 jc[4];
+        if (!JPF) load_j(v);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) jc[c] = jn[c];
+        if (v + 1 < nsub) {
+          if (JPF) load_j(v + 1);
+        }
         float rj[16], zj[8];
         float z = 0.0f;
-        const float2* pjt = jpts + 64 * v + 8 * b;
         if (diag_sb && v == us) {
-          sym_tile<true, ZROW>(xi, yi, pjt, rix, riy, zi, rj, zj, z, a == b);
+          sym_tile<true, ZROW>(xi, yi, jc, rix, riy, zi, rj, zj, z, a == b);
           zsum += double(z);
         } else {
-          sym_tile<false, ZROW>(xi, yi, pjt, rix, riy, zi, rj, zj, z, false);
+          // this tile's slot of the wave's j accumulator, read early
+          float2* dst = reinterpret_cast<float2*>(myj + comp * S + 64 * v + 8 * b + c0);
+          float2 cur = *dst;
+          sym_tile<false, ZROW>(xi, yi, jc, rix, riy, zi, rj, zj, z, false);
           zsum += 2.0 * double(z);
           // j side: reduce over the 8 lanes of this j-group, add into LDS
           float o0, o1;
           rs16_hi(rj, o0, o1);
-          const int comp = lane >> 5;
-          const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
-          float2* dst = reinterpret_cast<float2*>(myj + comp * S + 64 * v + 8 * b + c0);
-          float2 cur = *dst;
           cur.x += o0;
           cur.y += o1;
           *dst = cur;
@@ -361,17 +392,17 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       const int64_t pi_ = i0 + u, pj_ = j0 + u;
       if (diag_sb) {
         if (pi_ < n) {
-          reinterpret_cast<float2*>(part)[t * n + pi_] = make_float2(ix - jx, iy - jy);
-          if (ZROW) zpart[t * n + pi_] = iz + jz;
+          reinterpret_cast<float2*>(part)[part_index(pi_, t, ns, n, part_grouped(S))] = make_float2(ix - jx, iy - jy);
+          if (ZROW) zpart[part_index(pi_, t, ns, n, part_grouped(S))] = iz + jz;
         }
       } else {
         if (pi_ < n) {
-          reinterpret_cast<float2*>(part)[t * n + pi_] = make_float2(ix, iy);
-          if (ZROW) zpart[t * n + pi_] = iz;
+          reinterpret_cast<float2*>(part)[part_index(pi_, t, ns, n, part_grouped(S))] = make_float2(ix, iy);
+          if (ZROW) zpart[part_index(pi_, t, ns, n, part_grouped(S))] = iz;
         }
         if (pj_ < n) {
-          reinterpret_cast<float2*>(part)[s * n + pj_] = make_float2(-jx, -jy);
-          if (ZROW) zpart[s * n + pj_] = jz;
+          reinterpret_cast<float2*>(part)[part_index(pj_, s, ns, n, part_grouped(S))] = make_float2(-jx, -jy);
+          if (ZROW) zpart[part_index(pj_, s, ns, n, part_grouped(S))] = jz;
         }
       }
     }

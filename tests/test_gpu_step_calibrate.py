@@ -38,9 +38,8 @@ def entropy64(d2_row, beta):
     return np.log(S) + beta * (e * s).sum() / S
 
 
-# FP32 evaluation error of H at the returned beta (sums of k exp terms,
-# relative rounding of order k * 2^-24 on each sum, times H's sensitivity).
-H_FP32_SLACK = 2e-6
+# The kernel stops its FP32 search TSNE_CALIB_H_MARGIN inside tol, so the
+# entropy at the returned beta, recomputed in FP64, must be within tol.
 
 
 def test_calibrate_c1(dev):
@@ -52,7 +51,7 @@ def test_calibrate_c1(dev):
     assert conv.all() and int(nun.item()) == 0
     d64 = d2f.astype(np.float64)
     H = np.array([entropy64(d64[i], float(beta[i])) for i in range(d64.shape[0])])
-    assert np.abs(H - np.log(30.0)).max() <= 1e-5 + H_FP32_SLACK
+    assert np.abs(H - np.log(30.0)).max() <= 1e-5
     np.testing.assert_allclose(P.sum(1), 1.0, atol=2e-6)
     Po, _, _, _ = oracle.calibrate(d64, 30.0)
     assert np.abs(P - Po).max() <= 2e-5 * Po.max()
@@ -70,7 +69,7 @@ def test_calibrate_shapes(dev, n, k, perp):
     assert conv.all() and int(nun.item()) == 0
     d64 = d2.astype(np.float64)
     H = np.array([entropy64(d64[i], float(beta[i])) for i in range(n)])
-    assert np.abs(H - np.log(perp)).max() <= 1e-5 + H_FP32_SLACK
+    assert np.abs(H - np.log(perp)).max() <= 1e-5
     Po, _, _, _ = oracle.calibrate(d64, perp)
     assert np.abs(P - Po).max() <= 2e-5 * Po.max()
 
