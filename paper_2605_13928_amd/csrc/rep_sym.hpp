@@ -237,7 +237,6 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int a = lane >> 3, b = lane & 7;
   const int nsub = S / 64;
-  constexpr bool JPF = PF == 1;
   const int64_t njobs = ns * (ns + 1) / 2;
   const int64_t P = gridDim.x;
   float* myj = jacc + w * NC * S;
@@ -292,24 +291,14 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       for (int r = 0; r < 8; ++r) rix[r] = riy[r] = zi[r] = 0.0f;
       const int v0 = diag_sb ? us : 0;
       int since_fold = 0;
-      // j-points of the next tile are read from LDS while this one computes
-      // (when the registers allow it: JPF)
-      float4 jn[4];
-      auto load_j = [&](int v) {
-        const float4* p = reinterpret_cast<const float4*>(jpts + 64 * v + 8 * b);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) jn[c] = p[c];
-      };
-      if (JPF) load_j(v0);
       const int comp = lane >> 5;
       const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
       for (int v = v0; v < nsub; ++v) {
         float4 jc[4];
-        if (!JPF) load_j(v);
+        {
+          const float4* p = reinterpret_cast<const float4*>(jpts + 64 * v + 8 * b);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) jc[c] = jn[c];
-        if (v + 1 < nsub) {
-          if (JPF) load_j(v + 1);
+          for (int c = 0; c < 4; ++c) jc[c] = p[c];
         }
         float rj[16], zj[8];
         float z = 0.0f;
