@@ -208,12 +208,18 @@ typedef struct tsne_schedule {
  * exaggeration : 1), then the update of tsne_step with momentum_t =
  * (t < exaggeration_iters ? momentum_early : momentum_late).  The step runs
  * inside the gradient's last pass, and Y alternates with a workspace copy
- * (copied back at the end when the count is odd); the arithmetic is that of
- * the two entry points, so the result is bitwise identical to calling them
- * in a loop.
+ * (copied back at the end when the count is odd).  The attraction term is
+ * summed inside the all-pairs pass from a copy of P's upper triangle grouped
+ * by superblock pair (built once per call), in 64-bit fixed point
+ * (resolution 2^-56) and then rounded once, so it can differ from
+ * tsne_kl_grad's FP32 sum by FP32 rounding.  Logging the KL adds a CSR
+ * pass at the same Y and leaves the trajectory unchanged.  Deterministic.
  *   Y, update, gains  [n][2] float, updated in place (Y holds the result
  *                     when the enqueued work completes).  P as for
- *                     tsne_kl_grad.
+ *                     tsne_kl_grad, with a symmetric pattern, values >= 0
+ *                     and every row summing to at most 1 (true for the
+ *                     output of tsne_symmetrize).
+ *   nnz       stored entries of P (row_ptr[n]); it sizes the workspace.
  *   schedule  host pointer, read before the call returns.
  *   kl_log    device double array of (t_end - t_begin) entries (nullable):
  *             with log_every > 0, entry t - t_begin receives KL(P||Q) for the
@@ -224,8 +230,9 @@ typedef struct tsne_schedule {
  *             t's all-pairs repulsion kernel (the dominant cost), for timing.
  */
 int tsne_optimize(float* Y, float* update, float* gains, int64_t n, const int64_t* row_ptr, const int32_t* col,
-                  const float* val, int32_t t_begin, int32_t t_end, const tsne_schedule* schedule, int32_t log_every,
-                  double* kl_log, void* const* events, void* workspace, size_t* workspace_bytes, void* stream);
+                  const float* val, int64_t nnz, int32_t t_begin, int32_t t_end, const tsne_schedule* schedule,
+                  int32_t log_every, double* kl_log, void* const* events, void* workspace, size_t* workspace_bytes,
+                  void* stream);
 
 /*
  * Differentiation form.  KL(P||Q) as a function of the embedding Y and of

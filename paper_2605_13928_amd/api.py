@@ -215,8 +215,8 @@ def optimize(Y, update, gains, P: SparseP, t_begin: int, t_end: int, lr: float =
     L = _lib.load()
     _run_with_workspace("tsne_optimize", L.tsne_optimize,
                         (_ptr(Y), _ptr(update), _ptr(gains), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val),
-                         int(t_begin), int(t_end), C.byref(sc), int(log_every), _ptr(kl_log), ev_arr),
-                        (_stream(dev),), dev, ws, key=("optimize", n))
+                         int(P.nnz), int(t_begin), int(t_end), C.byref(sc), int(log_every), _ptr(kl_log), ev_arr),
+                        (_stream(dev),), dev, ws, key=("optimize", n, int(P.nnz)))
 
 
 def _dtype_code(t):

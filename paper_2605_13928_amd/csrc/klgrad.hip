@@ -8,6 +8,7 @@
 #include "common.hpp"
 #include "klgrad.hpp"
 #include "rep_sym.hpp"
+#include "scan.hpp"
 
 namespace tsne {
 
@@ -26,23 +27,27 @@ namespace tsne {
 // partials) are issued first.  Then
 // g_i = 4 (alpha A_i - R_i / Z); STEP: instead of storing g, apply the
 // optimiser step to the row (FusedStep).  Column indices outside [0, n)
-// contribute nothing.
+// contribute nothing.  ATTP: the attraction was summed per job by the
+// all-pairs kernel (AttList); it is read from its partial slices, exactly
+// like the repulsion, and the CSR is not touched.
 constexpr int FIN_ROWS = 16;
 constexpr int FIN_EPT = 8;
 constexpr int FIN_CHUNK = 256 * FIN_EPT;
 constexpr int FIN_PRE = 4;  // partial slices per thread loaded up front
 
-template <bool STEP>
+template <bool STEP, bool ATTP>
 __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     const float2* __restrict__ Y, int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, float alpha, const float2* __restrict__ Rpart, const float* __restrict__ Zrowpart,
-    int64_t ns, bool grouped, const double* __restrict__ Zblock, int64_t nZ, float2* __restrict__ grad,
-    double* __restrict__ Zrow, double* __restrict__ Z_out, double* __restrict__ klpart, FusedStep st) {
-  __shared__ float2 contrib[FIN_CHUNK];
+    const float2* __restrict__ Apart, int64_t ns, bool grouped, const double* __restrict__ Zblock, int64_t nZ,
+    float2* __restrict__ grad, double* __restrict__ Zrow, double* __restrict__ Z_out, double* __restrict__ klpart,
+    FusedStep st) {
+  constexpr int NPR = ATTP ? 5 : 3;  // per-thread sums: R x, R y, Z_row (, A x, A y)
+  __shared__ float2 contrib[ATTP ? 1 : FIN_CHUNK];
   __shared__ int64_t rps[FIN_ROWS + 1];
   __shared__ float2 yrow[FIN_ROWS];
   __shared__ double red[4];
-  __shared__ double pr[16][FIN_ROWS][3];
+  __shared__ double pr[16][FIN_ROWS][NPR];
   __shared__ float2 att[FIN_ROWS];
   const int tid = threadIdx.x;
   const int g = tid >> 4, sl = tid & 15;
@@ -52,11 +57,13 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
   // --- loads with no dependences -----------------------------------------
   if (tid <= FIN_ROWS) rps[tid] = row_ptr[r0 + tid < n ? r0 + tid : n];
   if (tid < FIN_ROWS) yrow[tid] = r0 + tid < n ? Y[r0 + tid] : make_float2(0.0f, 0.0f);
-  float2 rpv[FIN_PRE];
+  float2 rpv[FIN_PRE], apv[FIN_PRE];
 #pragma unroll
   for (int u = 0; u < FIN_PRE; ++u) {
     const int64_t k = g + 16 * u;
-    rpv[u] = (prow < n && k < ns) ? Rpart[part_index(prow, k, ns, n, grouped)] : make_float2(0.0f, 0.0f);
+    const bool ok = prow < n && k < ns;
+    rpv[u] = ok ? Rpart[part_index(prow, k, ns, n, grouped)] : make_float2(0.0f, 0.0f);
+    apv[u] = (ATTP && ok) ? Apart[part_index(prow, k, ns, n, grouped)] : make_float2(0.0f, 0.0f);
   }
   const double zt = zblock_thread_sum(Zblock, nZ);
   __syncthreads();
@@ -65,7 +72,7 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
   const int64_t E0 = rps[0], E1 = rps[FIN_ROWS];
   const int64_t ga = rps[g], gb = rps[g + 1];
   float ax = 0.0f, ay = 0.0f, plp = 0.0f, plq = 0.0f, ps = 0.0f;
-  for (int64_t c0 = E0; c0 < E1; c0 += FIN_CHUNK) {
+  for (int64_t c0 = E0; !ATTP && c0 < E1; c0 += FIN_CHUNK) {
     int32_t jj[FIN_EPT];
     float pp[FIN_EPT];
 #pragma unroll
@@ -122,28 +129,44 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
 
   // --- repulsion partials: slices g, g + 16, ... in order ------------------
   {
-    double rx = 0.0, ry = 0.0, zr = 0.0;
+    double rx = 0.0, ry = 0.0, zr = 0.0, axd = 0.0, ayd = 0.0;
 #pragma unroll
     for (int u = 0; u < FIN_PRE; ++u) {
       rx += double(rpv[u].x);
       ry += double(rpv[u].y);
+      if (ATTP) {
+        axd += double(apv[u].x);
+        ayd += double(apv[u].y);
+      }
     }
     if (prow < n) {
       int64_t k = g + 16 * FIN_PRE;
       for (; k + 48 < ns; k += 64) {
-        float2 rr[4];
+        float2 rr[4], aa[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) rr[u] = Rpart[part_index(prow, k + 16 * u, ns, n, grouped)];
+        for (int u = 0; u < 4; ++u) {
+          rr[u] = Rpart[part_index(prow, k + 16 * u, ns, n, grouped)];
+          if (ATTP) aa[u] = Apart[part_index(prow, k + 16 * u, ns, n, grouped)];
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           rx += double(rr[u].x);
           ry += double(rr[u].y);
+          if (ATTP) {
+            axd += double(aa[u].x);
+            ayd += double(aa[u].y);
+          }
         }
       }
       for (; k < ns; k += 16) {
         const float2 rr = Rpart[part_index(prow, k, ns, n, grouped)];
         rx += double(rr.x);
         ry += double(rr.y);
+        if (ATTP) {
+          const float2 aa = Apart[part_index(prow, k, ns, n, grouped)];
+          axd += double(aa.x);
+          ayd += double(aa.y);
+        }
       }
       if (Zrow)
         for (int64_t kk = g; kk < ns; kk += 16) zr += double(Zrowpart[part_index(prow, kk, ns, n, grouped)]);
@@ -151,6 +174,10 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     pr[g][sl][0] = rx;
     pr[g][sl][1] = ry;
     pr[g][sl][2] = zr;
+    if (ATTP) {
+      pr[g][sl][3 % NPR] = axd;
+      pr[g][sl][4 % NPR] = ayd;
+    }
   }
   ax = row16_sum(ax);
   ay = row16_sum(ay);
@@ -158,16 +185,23 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
   const double Z = block_sum_d(zt, red);  // its barriers also publish pr and att
   if (blockIdx.x == 0 && tid == 0 && Z_out) *Z_out = Z;
   if (tid < FIN_ROWS && r0 + tid < n) {
-    double Rx = 0.0, Ry = 0.0, Zr = 0.0;
+    double Rx = 0.0, Ry = 0.0, Zr = 0.0, Ax = 0.0, Ay = 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       Rx += pr[k][tid][0];
       Ry += pr[k][tid][1];
       Zr += pr[k][tid][2];
+      if (ATTP) {
+        Ax += pr[k][tid][3 % NPR];
+        Ay += pr[k][tid][4 % NPR];
+      }
     }
-    const float2 a = att[tid];
-    const float2 gi = make_float2(float(4.0 * (double(alpha) * double(a.x) - Rx / Z)),
-                                  float(4.0 * (double(alpha) * double(a.y) - Ry / Z)));
+    if (!ATTP) {
+      Ax = double(att[tid].x);
+      Ay = double(att[tid].y);
+    }
+    const float2 gi = make_float2(float(4.0 * (double(alpha) * Ax - Rx / Z)),
+                                  float(4.0 * (double(alpha) * Ay - Ry / Z)));
     const int64_t i = r0 + tid;
     if (STEP) {
       step_coord(sy.x, su.x, sg.x, gi.x, st.lr, st.mom, st.inc, st.dec, st.mn);
@@ -210,7 +244,7 @@ __global__ __launch_bounds__(256) void kl_reduce_kernel(const double* __restrict
   if (threadIdx.x == 0) *kl_out = a + b + c * log(Z);
 }
 
-KlGradPlan klgrad_plan(int64_t n) {
+KlGradPlan klgrad_plan(int64_t n, bool with_att) {
   KlGradPlan L;
   L.g = SymGrid::make(n);
   L.nfin = ceil_div(n, FIN_ROWS);
@@ -220,31 +254,116 @@ KlGradPlan klgrad_plan(int64_t n) {
   L.o_Zr = c.take(sizeof(float) * size_t(L.g.ns) * n16);
   L.o_Zb = c.take(sizeof(double) * size_t(L.g.nwg));
   L.o_kl = c.take(sizeof(double) * 3 * size_t(L.nfin));
+  L.o_A = with_att ? c.take(sizeof(float2) * size_t(L.g.ns) * n16) : 0;
+  L.o_g = with_att ? c.take(sizeof(float2) * size_t(n)) : 0;
   L.bytes = c.off;
   return L;
 }
 
+// --- job-grouped attraction list ------------------------------------------
+
+__device__ __forceinline__ int64_t job_of(int64_t s, int64_t t, int64_t ns) {
+  return s == t ? ns * (ns - 1) / 2 + s : t * (t - 1) / 2 + s;  // inverse of job_pair
+}
+
+// One wave per row i: entries (i, j) with j > i, counted per job.
+__global__ __launch_bounds__(256) void att_count_kernel(int64_t n, int64_t S, int64_t ns,
+                                                        const int64_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col, int* __restrict__ cnt) {
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  for (int64_t e = row_ptr[i] + lane_id(); e < row_ptr[i + 1]; e += 64) {
+    const int32_t j = col[e];
+    if (j > i && j < n) atomicAdd(&cnt[job_of(i / S, j / S, ns)], 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void att_scatter_kernel(int64_t n, int64_t S, int64_t ns,
+                                                          const int64_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const float* __restrict__ val,
+                                                          const int64_t* __restrict__ off, int* __restrict__ cur,
+                                                          uint32_t* __restrict__ ij, float* __restrict__ p,
+                                                          int64_t cap) {
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  for (int64_t e = row_ptr[i] + lane_id(); e < row_ptr[i + 1]; e += 64) {
+    const int32_t j = col[e];
+    if (j > i && j < n) {
+      const int64_t s = i / S, t = j / S, q = job_of(s, t, ns);
+      const int64_t pos = off[q] + atomicAdd(&cur[q], 1);
+      if (pos < cap) {  // cap < entries only if the caller's nnz is wrong
+        ij[pos] = uint32_t(i - s * S) | (uint32_t(j - t * S) << 16);
+        p[pos] = val[e];
+      }
+    }
+  }
+}
+
+AttPlan att_plan(const SymGrid& g, int64_t nnz) {
+  AttPlan A;
+  Carve c;
+  const size_t nb = size_t(ceil_div(g.njobs + 1, SCAN_CHUNK)) + 1;
+  A.o_cnt = c.take(sizeof(int) * size_t(g.njobs));
+  A.o_cur = c.take(sizeof(int) * size_t(g.njobs));
+  A.o_off = c.take(sizeof(int64_t) * (size_t(g.njobs) + 1));
+  A.o_bsum = c.take(sizeof(int64_t) * nb);
+  A.o_ij = c.take(sizeof(uint32_t) * size_t(nnz > 0 ? nnz : 1));
+  A.o_p = c.take(sizeof(float) * size_t(nnz > 0 ? nnz : 1));
+  A.bytes = c.off;
+  return A;
+}
+
+int att_build(const AttPlan& A, const SymGrid& g, char* ws, int64_t n, const int64_t* row_ptr, const int32_t* col,
+              const float* val, AttList* out, hipStream_t s) {
+  int* cnt = reinterpret_cast<int*>(ws + A.o_cnt);
+  int* cur = reinterpret_cast<int*>(ws + A.o_cur);
+  int64_t* off = reinterpret_cast<int64_t*>(ws + A.o_off);
+  int64_t* bsum = reinterpret_cast<int64_t*>(ws + A.o_bsum);
+  uint32_t* ij = reinterpret_cast<uint32_t*>(ws + A.o_ij);
+  float* p = reinterpret_cast<float*>(ws + A.o_p);
+  int rc;
+  if ((rc = launch_fill<int>(cnt, g.njobs, 0, s))) return rc;
+  if ((rc = launch_fill<int>(cur, g.njobs, 0, s))) return rc;
+  const dim3 grid(unsigned(ceil_div(n, 4))), block(256);
+  hipLaunchKernelGGL(att_count_kernel, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, cnt);
+  TSNE_CHECK_LAUNCH();
+  if ((rc = exclusive_scan<int>(cnt, g.njobs, off, bsum, s))) return rc;
+  const int64_t cap = int64_t((A.o_p - A.o_ij) / sizeof(uint32_t));
+  hipLaunchKernelGGL(att_scatter_kernel, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, val, off, cur, ij, p, cap);
+  TSNE_CHECK_LAUNCH();
+  *out = AttList{off, ij, p, cap};
+  return TSNE_OK;
+}
+
 int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, const int64_t* row_ptr,
                   const int32_t* col, const float* val, float alpha, float* grad, double* Z, double* kl, double* Zrow,
-                  hipStream_t s, const FusedStep* step, hipEvent_t after_repulsion) {
+                  hipStream_t s, const FusedStep* step, hipEvent_t after_repulsion, const AttList* att) {
   const SymGrid& g = L.g;
+  const bool fused = att && !Zrow && L.o_A;
   float* Rpart = reinterpret_cast<float*>(ws + L.o_R);
   float* Zrowpart = Zrow ? reinterpret_cast<float*>(ws + L.o_Zr) : nullptr;
   double* Zblock = reinterpret_cast<double*>(ws + L.o_Zb);
   double* klpart = kl ? reinterpret_cast<double*>(ws + L.o_kl) : nullptr;
+  float2* Apart = fused ? reinterpret_cast<float2*>(ws + L.o_A) : nullptr;
+  const AttList al = fused ? *att : AttList{nullptr, nullptr, nullptr, 0};
   const float2* Y2 = reinterpret_cast<const float2*>(Y);
-  const size_t lds = rep_sym_lds_bytes(g.S, Zrow != nullptr);
+  const size_t lds = rep_sym_lds_bytes(g.S, Zrow != nullptr, fused);
   const dim3 grid(unsigned(g.nwg)), block(256);
-#define TSNE_REP_SYM(Z, PF) \
-  hipLaunchKernelGGL((rep_sym_kernel<Z, PF>), grid, block, lds, s, Y2, n, g.ns, Rpart, Zrowpart, Zblock)
+#define TSNE_REP_SYM(Z, PF, A) \
+  hipLaunchKernelGGL((rep_sym_kernel<Z, PF, A>), grid, block, lds, s, Y2, n, g.ns, Rpart, Zrowpart, Zblock, al, Apart)
   if (Zrow) {
-    if (g.S == 256) TSNE_REP_SYM(true, 1);
-    else if (g.S == 512) TSNE_REP_SYM(true, 2);
-    else TSNE_REP_SYM(true, 4);
+    if (g.S == 256) TSNE_REP_SYM(true, 1, false);
+    else if (g.S == 512) TSNE_REP_SYM(true, 2, false);
+    else TSNE_REP_SYM(true, 4, false);
+  } else if (fused) {
+    if (g.S == 256) TSNE_REP_SYM(false, 1, true);
+    else if (g.S == 512) TSNE_REP_SYM(false, 2, true);
+    else TSNE_REP_SYM(false, 4, true);
   } else {
-    if (g.S == 256) TSNE_REP_SYM(false, 1);
-    else if (g.S == 512) TSNE_REP_SYM(false, 2);
-    else TSNE_REP_SYM(false, 4);
+    if (g.S == 256) TSNE_REP_SYM(false, 1, false);
+    else if (g.S == 512) TSNE_REP_SYM(false, 2, false);
+    else TSNE_REP_SYM(false, 4, false);
   }
 #undef TSNE_REP_SYM
   TSNE_CHECK_LAUNCH();
@@ -255,14 +374,28 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
       return TSNE_ERR_HIP;
     }
   }
-  if (step)
-    hipLaunchKernelGGL(finalize_tsne_kernel<true>, dim3(unsigned(L.nfin)), dim3(256), 0, s, Y2, n, row_ptr, col, val,
-                       alpha, reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, part_grouped(g.S), Zblock,
-                       g.nwg, nullptr, Zrow, Z, klpart, *step);
-  else
-    hipLaunchKernelGGL(finalize_tsne_kernel<false>, dim3(unsigned(L.nfin)), dim3(256), 0, s, Y2, n, row_ptr, col,
-                       val, alpha, reinterpret_cast<const float2*>(Rpart), Zrowpart, g.ns, part_grouped(g.S), Zblock,
-                       g.nwg, reinterpret_cast<float2*>(grad), Zrow, Z, klpart, FusedStep{});
+  const dim3 fgrid(unsigned(L.nfin));
+  const float2* R2 = reinterpret_cast<const float2*>(Rpart);
+  const bool grp = part_grouped(g.S);
+  float2* gr = reinterpret_cast<float2*>(grad);
+  const FusedStep st = step ? *step : FusedStep{};
+#define TSNE_FIN(STEP, A, GR, KLP)                                                                          \
+  hipLaunchKernelGGL((finalize_tsne_kernel<STEP, A>), fgrid, block, 0, s, Y2, n, row_ptr, col, val, alpha, R2, \
+                     Zrowpart, Apart, g.ns, grp, Zblock, g.nwg, GR, Zrow, Z, KLP, st)
+  if (fused) {
+    if (step) TSNE_FIN(true, true, nullptr, nullptr);
+    else TSNE_FIN(false, true, gr, nullptr);
+    if (kl) {
+      // the KL sums come from the CSR pass, at the same Y; its gradient
+      // output goes to scratch, so logging does not change the trajectory
+      TSNE_CHECK_LAUNCH();
+      TSNE_FIN(false, false, reinterpret_cast<float2*>(ws + L.o_g), klpart);
+    }
+  } else {
+    if (step) TSNE_FIN(true, false, nullptr, klpart);
+    else TSNE_FIN(false, false, gr, klpart);
+  }
+#undef TSNE_FIN
   TSNE_CHECK_LAUNCH();
   if (kl) {
     hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, klpart, L.nfin, Zblock, g.nwg, kl);

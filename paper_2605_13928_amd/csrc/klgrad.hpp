@@ -32,19 +32,33 @@ struct FusedStep {
 struct KlGradPlan {
   SymGrid g;
   int64_t nfin;
-  size_t o_R, o_Zr, o_Zb, o_kl, bytes;
+  size_t o_R, o_Zr, o_Zb, o_kl, o_A, o_g, bytes;  // o_A, o_g: attraction partials, scratch gradient (with_att)
 };
 
-// Workspace layout of one gradient evaluation for n points.
-KlGradPlan klgrad_plan(int64_t n);
+// Workspace layout of one gradient evaluation for n points; with_att adds
+// the attraction partials of the fused path (AttList).
+KlGradPlan klgrad_plan(int64_t n, bool with_att = false);
+
+// Workspace layout and build of the job-grouped attraction list of a CSR P
+// with nnz stored entries (unordered pairs i < j; see AttList).
+struct AttPlan {
+  size_t o_cnt, o_cur, o_off, o_bsum, o_ij, o_p, bytes;
+};
+AttPlan att_plan(const SymGrid& g, int64_t nnz);
+int att_build(const AttPlan& A, const SymGrid& g, char* ws, int64_t n, const int64_t* row_ptr, const int32_t* col,
+              const float* val, AttList* out, hipStream_t s);
 
 // Enqueue one gradient evaluation (arguments as tsne_kl_grad, validated).
 // With `step`, the finalize pass applies the optimiser step to every row
 // instead of writing the gradient (grad may then be null).  after_repulsion
 // (nullable) is recorded on s between the all-pairs pass and the finalize.
+// With `att` (plan made with_att; Zrow not requested) the attraction is
+// summed inside the all-pairs kernel from the job-grouped list; a requested
+// KL then comes from an extra CSR pass at the same Y.
 int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, const int64_t* row_ptr,
                   const int32_t* col, const float* val, float alpha, float* grad, double* Z, double* kl, double* Zrow,
-                  hipStream_t s, const FusedStep* step = nullptr, hipEvent_t after_repulsion = nullptr);
+                  hipStream_t s, const FusedStep* step = nullptr, hipEvent_t after_repulsion = nullptr,
+                  const AttList* att = nullptr);
 
 // Enqueue one optimiser step (arguments as tsne_step, validated).
 int step_launch(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr, float momentum,

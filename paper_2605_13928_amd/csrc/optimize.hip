@@ -4,32 +4,39 @@
 // 2008 (Sec. 3.4, Algorithm 1): early exaggeration and the lower momentum
 // while t < exaggeration_iters.  The step is applied by the gradient's
 // finalize pass (one launch fewer per iteration); the embedding ping-pongs
-// between Y and a workspace copy, because that pass still gathers the old
-// positions of other rows while it writes new ones.  Same arithmetic as the
-// separate calls, so results are bitwise identical to calling them in a loop.
+// between Y and a workspace copy, because that pass still reads the old
+// positions of other rows while it writes new ones.  The attraction is
+// summed inside the all-pairs kernel from a job-grouped copy of P's upper
+// triangle, built once per call (no per-iteration gathers of y_j); on the
+// iterations that log the KL an extra CSR pass at the same Y adds the KL
+// sums without changing the trajectory.
 #include "common.hpp"
 #include "klgrad.hpp"
 
 extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, const int64_t* row_ptr,
-                             const int32_t* col, const float* val, int32_t t_begin, int32_t t_end,
+                             const int32_t* col, const float* val, int64_t nnz, int32_t t_begin, int32_t t_end,
                              const tsne_schedule* schedule, int32_t log_every, double* kl_log, void* const* events,
                              void* workspace, size_t* workspace_bytes, void* stream) {
   using namespace tsne;
-  if (!Y || !update || !gains || !row_ptr || !col || !val || !schedule || n < 2) return TSNE_ERR_INVALID_ARG;
+  if (!Y || !update || !gains || !row_ptr || !col || !val || !schedule || n < 2 || nnz < 0) return TSNE_ERR_INVALID_ARG;
   if (t_begin < 0 || t_end < t_begin || log_every < 0) return TSNE_ERR_INVALID_ARG;
   const tsne_schedule sc = *schedule;
   if (!(sc.exaggeration > 0.0f) || !(sc.exaggeration < INFINITY) || !(sc.lr > 0.0f)) return TSNE_ERR_INVALID_ARG;
   if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
-  const KlGradPlan L = klgrad_plan(n);
+  const KlGradPlan L = klgrad_plan(n, true);
+  const AttPlan A = att_plan(L.g, nnz);
   Carve c;
   const size_t o_kg = c.take(L.bytes);
   const size_t o_y = c.take(sizeof(float) * 2 * size_t(n));
+  const size_t o_att = c.take(A.bytes);
   int rc = workspace_protocol(workspace, workspace_bytes, c.off);
   if (rc >= 0) return rc;
   char* ws = static_cast<char*>(workspace);
   float* ycur = Y;
   float* ynext = reinterpret_cast<float*>(ws + o_y);
   hipStream_t s = as_stream(stream);
+  AttList att;
+  if (t_end > t_begin && (rc = att_build(A, L.g, ws + o_att, n, row_ptr, col, val, &att, s))) return rc;
   for (int32_t t = t_begin; t < t_end; ++t) {
     const bool early = t < sc.exaggeration_iters;
     const float alpha = early ? sc.exaggeration : 1.0f;
@@ -44,7 +51,7 @@ extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, c
                        reinterpret_cast<float2*>(gains), sc.lr, mom, sc.gain_inc, sc.gain_dec, sc.min_gain};
     rc = klgrad_launch(L, ws + o_kg, ycur, n, row_ptr, col, val, alpha, nullptr, nullptr,
                        log ? kl_log + slot : nullptr, nullptr, s, &st,
-                       events ? static_cast<hipEvent_t>(events[2 * slot + 1]) : nullptr);
+                       events ? static_cast<hipEvent_t>(events[2 * slot + 1]) : nullptr, &att);
     if (rc) return rc;
     float* tmp = ycur;
     ycur = ynext;

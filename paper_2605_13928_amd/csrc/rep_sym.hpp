@@ -220,12 +220,27 @@ __device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)
 
 // LDS layout of a workgroup (floats): ipts[2*S] | jpts[2*S] | iacc[NC*S] |
 // jacc[4][NC*S] with NC = 2 (x, y) or 3 (x, y, Z_row), component-major per
-// accumulator.
+// accumulator; with ATT then aacc[4][S] (64-bit).
 // PF = S / 256: points per thread and side.
-template <bool ZROW, int PF>
+// Attraction entries grouped by job (built once per P): job q owns entries
+// [off[q], off[q + 1]); entry e is the unordered pair {i, j}, i < j, with
+// local indices packed as (i - s S) | (j - t S) << 16, and its value p_ij.
+struct AttList {
+  const int64_t* off;
+  const uint32_t* ij;
+  const float* p;
+  int64_t cap;  // entries the list can hold; offsets are clamped to it
+};
+
+// Fixed-point scale of the attraction sums (see the ATT phase below).
+constexpr float ATT_SCALE = 0x1p56f;
+
+template <bool ZROW, int PF, bool ATT>
 __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__ Y, int64_t n, int64_t ns,
                                                       float* __restrict__ part, float* __restrict__ zpart,
-                                                      double* __restrict__ Zblock) {
+                                                      double* __restrict__ Zblock, AttList att,
+                                                      float2* __restrict__ apart) {
+  static_assert(!(ATT && ZROW), "the fused attraction is for the gradient-only launch");
   constexpr int NC = ZROW ? 3 : 2;
   constexpr int S = 256 * PF;
   extern __shared__ __attribute__((aligned(16))) float lds[];
@@ -234,6 +249,12 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
   float2* jpts = ipts + S;
   float* iacc = lds + 4 * S;
   float* jacc = iacc + NC * S;
+  // attraction sums of the job in 64-bit fixed point: i x, i y, j x, j y.
+  // Small superblocks have room for a separate array; the largest reuse the
+  // j accumulators before the pair tiles need them (ATT_SEP false).
+  constexpr bool ATT_SEP = PF < 4;
+  constexpr bool ATT_PRE = ATT && PF < 4;  // registers allow the entry prefetch
+  unsigned long long* aacc = reinterpret_cast<unsigned long long*>(ATT_SEP ? jacc + SYM_WAVES * NC * S : jacc);
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int a = lane >> 3, b = lane & 7;
   const int nsub = S / 64;
@@ -253,11 +274,58 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       pj[k] = load_point(Y, t * S + u, n);
     }
   };
+  // attraction entries: the next job's range and first two entries per
+  // thread are loaded while the current job computes
+  int64_t ne0 = 0, ne1 = 0;
+  uint32_t npk[2] = {0u, 0u};
+  float npv[2] = {0.0f, 0.0f};
+  auto fetch_range = [&](int64_t q) {
+    ne0 = min(att.off[q], att.cap);
+    ne1 = min(att.off[q + 1], att.cap);
+  };
+  auto fetch_entries = [&]() {
+    if (!ATT_PRE) return;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int64_t e = ne0 + tid + 256 * m;
+      npk[m] = e < ne1 ? att.ij[e] : 0u;
+      npv[m] = e < ne1 ? att.p[e] : 0.0f;
+    }
+  };
+
+  // attraction partials of job (s, t): the exact fixed-point sums, rounded
+  // once; the accumulators are cleared for the next use
+  auto write_att = [&](int64_t s, int64_t t, bool diag_sb) {
+    const double sc = 1.0 / double(ATT_SCALE);
+    for (int u = tid; u < S; u += 256) {
+      const double aix = double((long long)aacc[u]), aiy = double((long long)aacc[S + u]);
+      const double ajx = double((long long)aacc[2 * S + u]), ajy = double((long long)aacc[3 * S + u]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) aacc[c * S + u] = 0ull;
+      const int64_t pi_ = s * S + u, pj_ = t * S + u;
+      if (diag_sb) {
+        if (pi_ < n)
+          apart[part_index(pi_, t, ns, n, part_grouped(S))] =
+              make_float2(float((aix + ajx) * sc), float((aiy + ajy) * sc));
+      } else {
+        if (pi_ < n) apart[part_index(pi_, t, ns, n, part_grouped(S))] = make_float2(float(aix * sc), float(aiy * sc));
+        if (pj_ < n) apart[part_index(pj_, s, ns, n, part_grouped(S))] = make_float2(float(ajx * sc), float(ajy * sc));
+      }
+    }
+  };
 
   int64_t q = blockIdx.x;
-  if (q < njobs) fetch(q);
+  if (q < njobs) {
+    fetch(q);
+    if (ATT_PRE) {
+      fetch_range(q);
+      fetch_entries();
+    }
+  }
   for (int u = tid; u < NC * S; u += 256) iacc[u] = 0.0f;
   for (int u = tid; u < SYM_WAVES * NC * S; u += 256) jacc[u] = 0.0f;
+  if (ATT_SEP && ATT)
+    for (int u = tid; u < 4 * S; u += 256) aacc[u] = 0ull;
   double zsum = 0.0;
   for (; q < njobs; q += P) {
     int64_t s, t;
@@ -271,6 +339,43 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
     }
     __syncthreads();  // points staged, accumulators zeroed
     if (q + P < njobs) fetch(q + P);  // lands while this job computes
+
+    if (ATT) {
+      // Attraction of the job's P entries, A_i += p w (y_i - y_j) and
+      // A_j -= p w (y_i - y_j), from the staged points, before the pair
+      // tiles.  The sums are kept in 64-bit fixed point (scale 2^56), so
+      // the integer LDS atomics give an exact, order-independent
+      // (deterministic) result; |p w (y_i - y_j)| <= p / 2 and a row's p
+      // sum to at most 1 keep every sum below 2^55.
+      if (!ATT_PRE) fetch_range(q);  // (no prefetch: keep registers free)
+      const int64_t ae0 = ne0, ae1 = ne1;
+      const uint32_t pk0 = npk[0], pk1 = npk[1];
+      const float pv0 = npv[0], pv1 = npv[1];
+      if (ATT_PRE && q + P < njobs) fetch_range(q + P);  // used after the tiles
+      auto add_entry = [&](uint32_t pk, float pv) {
+        const int il = int(pk & 0xFFFFu), jl = int(pk >> 16);
+        const float2 yi = ipts[il], yj = jpts[jl];
+        const float dx = yi.x - yj.x, dy = yi.y - yj.y;
+        const float c = pv * __builtin_amdgcn_rcpf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f)));
+        const long long fx = __float2ll_rn(c * dx * ATT_SCALE), fy = __float2ll_rn(c * dy * ATT_SCALE);
+        atomicAdd(&aacc[il], (unsigned long long)fx);
+        atomicAdd(&aacc[S + il], (unsigned long long)fy);
+        atomicAdd(&aacc[2 * S + jl], (unsigned long long)(-fx));
+        atomicAdd(&aacc[3 * S + jl], (unsigned long long)(-fy));
+      };
+      int64_t e = ae0 + tid;
+      if (ATT_PRE) {
+        if (e < ae1) add_entry(pk0, pv0);
+        if (e + 256 < ae1) add_entry(pk1, pv1);
+        e += 512;
+      }
+      for (; e < ae1; e += 256) add_entry(att.ij[e], att.p[e]);
+      if (!ATT_SEP) {
+        __syncthreads();
+        write_att(s, t, diag_sb);  // and clear: the pair tiles accumulate there next
+        __syncthreads();
+      }
+    }
 
     for (int us = w; us < nsub; us += SYM_WAVES) {
       // this wave's i-subblock us: points s S + 64 us + 8a + r
@@ -358,6 +463,8 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
         }
       }
     }
+    // the next job's first attraction entries (its range arrived meanwhile)
+    if (ATT_PRE && q + P < njobs) fetch_entries();
     __syncthreads();  // job's accumulators complete; staged points free
 
     // write the partials part[t][i in s] and part[s][j in t]; each thread
@@ -395,14 +502,16 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
         }
       }
     }
+    if (ATT_SEP && ATT) write_att(s, t, diag_sb);  // its atomics finished before the barrier above
   }
   const double bz = block_sum_d(zsum, red);
   if (tid == 0) Zblock[blockIdx.x] = bz;
 }
 
-inline size_t rep_sym_lds_bytes(int64_t S, bool zrow) {
+inline size_t rep_sym_lds_bytes(int64_t S, bool zrow, bool att) {
   const int nc = zrow ? 3 : 2;
-  return sizeof(float) * size_t(S) * size_t(4 + nc + SYM_WAVES * nc);
+  const bool sep = att && S < 1024;  // ATT_SEP of the kernel
+  return sizeof(float) * size_t(S) * size_t(4 + nc + SYM_WAVES * nc) + (sep ? 4 * sizeof(uint64_t) * size_t(S) : 0);
 }
 
 }  // namespace tsne

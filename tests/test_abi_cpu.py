@@ -103,11 +103,16 @@ def test_invalid_arguments_rejected(L):
     sc = _lib.Schedule(200.0, 12.0, 100, 0.5, 0.8, 0.2, 0.8, 0.01)
     bad_sc = _lib.Schedule(200.0, 0.0, 100, 0.5, 0.8, 0.2, 0.8, 0.01)
     opt = L.tsne_optimize
-    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 0, 10, C.byref(sc), 0, NULL, NULL)[0] == 0
-    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 0, 10, None, 0, NULL, NULL)[0] == IA
-    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 5, 4, C.byref(sc), 0, NULL, NULL)[0] == IA
-    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 0, 10, C.byref(bad_sc), 0, NULL, NULL)[0] == IA
-    assert ws_query(opt, NULL, fake, fake, 100, fake, fake, fake, 0, 10, C.byref(sc), 0, NULL, NULL)[0] == IA
+    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 900, 0, 10, C.byref(sc), 0, NULL, NULL)[0] == 0
+    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 900, 0, 10, None, 0, NULL, NULL)[0] == IA
+    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 900, 5, 4, C.byref(sc), 0, NULL, NULL)[0] == IA
+    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 900, 0, 10, C.byref(bad_sc), 0, NULL, NULL)[0] == IA
+    assert ws_query(opt, NULL, fake, fake, 100, fake, fake, fake, 900, 0, 10, C.byref(sc), 0, NULL, NULL)[0] == IA
+    assert ws_query(opt, fake, fake, fake, 100, fake, fake, fake, -1, 0, 10, C.byref(sc), 0, NULL, NULL)[0] == IA
+    # the workspace grows with nnz (the job-grouped attraction list)
+    small = ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 900, 0, 10, C.byref(sc), 0, NULL, NULL)[1]
+    big = ws_query(opt, fake, fake, fake, 100, fake, fake, fake, 90000, 0, 10, C.byref(sc), 0, NULL, NULL)[1]
+    assert big - small >= 8 * (90000 - 900) - 512
     # differentiation form
     assert ws_query(L.tsne_kl_forward, 5, fake, 64, fake, fake, fake, fake, NULL)[0] == IA  # dtype
     assert ws_query(L.tsne_kl_backward, 0, fake, 64, fake, fake, fake, NULL, fake, fake, NULL)[0] == IA  # tpos

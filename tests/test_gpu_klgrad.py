@@ -97,3 +97,31 @@ def test_klgrad_c5_sampled_rows(dev):
     go = 4.0 * (Ao - Ro / Zg)
     e = rel(g.cpu().numpy()[rows], go)
     assert e <= GRAD_RTOL, e
+
+
+@pytest.mark.parametrize("n", [20_000, 50_000, 100_003])
+def test_fused_attraction_first_iteration(dev, n):
+    # tsne_optimize sums the attraction inside the all-pairs kernel (one
+    # launch configuration per superblock size: 256, 512, 1024 here).  At
+    # t = 0 the update is -lr * 0.8 * g exactly up to FP32 rounding, so the
+    # gradient is recovered from it and checked row by row against the
+    # oracle's A_i, R_i (alpha = 12), with Z from tsne_kl_grad at the same Y.
+    say("fused attraction", n)
+    idx, d2, Pc, S = random_graph_P(n, 90, 30.0, 7)
+    So = widen(S, S.val.astype(np.float32))
+    P = sparse_to_dev(So, dev)
+    Y = synth.random_embedding(n, 5.0, 3000 + n % 97)
+    Yd = to_dev(Y, dev)
+    _, Z, _, _ = api.kl_grad(Yd, P, 12.0, want_Z=True)
+    Yo = Yd.clone()
+    U = torch.zeros_like(Yo)
+    G = torch.ones_like(Yo)
+    api.optimize(Yo, U, G, P, 0, 1, lr=200.0, exaggeration=12.0)
+    g = -U.cpu().numpy().astype(np.float64) / (200.0 * 0.8)
+    rows = np.random.default_rng(n).choice(n, 256, replace=False)
+    Zo, Ro, Ao = oracle.grad_rows(Y.astype(np.float64), rows, So)
+    go = 4.0 * (12.0 * Ao - Ro / Z.item())
+    e = rel(g[rows], go)
+    assert e <= GRAD_RTOL, e
+    # and the step itself: Y + update
+    np.testing.assert_array_equal(Yo.cpu().numpy(), (Yd + U).cpu().numpy())
