@@ -333,8 +333,8 @@ __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r 
 
 // Block = 4 waves x 64 queries.  Lane l works on queries 16 t + (l % 16),
 // t = 0..3, of its wave and, per 16-candidate subtile, on candidates
-// 4 (l / 16) .. + 3 (the MFMA C layout).  A query's threshold is held
-// (identically) by its four lanes; its count is in LDS.
+// 4 (l / 16) .. + 3 (the MFMA C layout).  A query's threshold and buffer
+// count are held (identically) by its four lanes.
 template <int EPL>
 __global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
                                                        int64_t n, int ncand, uint64_t* __restrict__ bufs,
@@ -342,12 +342,11 @@ __global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restric
   constexpr int CAP = 64 * EPL;
   __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
   __shared__ uint32_t hist_s[4][256];   // per-wave radix-select histograms
-  __shared__ int cnt_s[256];            // buffer counts (appended by LDS atomics)
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q16 = lane & 15, g4 = lane >> 4;
   const int64_t qblock = int64_t(blockIdx.x) * 256;
   const int64_t qbase = qblock + w * 64;
-  cnt_s[tid] = 0;  // published by the first tile barrier
+  int cnt[4] = {0, 0, 0, 0};  // buffer count of query (t, q16), the same in its four lanes
   // query fragments: tile t, k-step s; lane holds query qbase + 16 t + q16,
   // k elements 32 s + 8 g4 ... + 7
   bf16x8_t bq[4][2];
@@ -420,49 +419,68 @@ __global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restric
             p[r] = acc[t][r] <= tau[t] && (!edge || (jb + r < n && jb + r != qi));
             c += int(p[r]);
           }
-          if (c) {
-            int pos = atomicAdd(&cnt_s[w * 64 + t * 16 + q16], c);
-            uint64_t* qbuf = bufs + qi * CAP;
+          if (__ballot(c != 0) == 0) continue;
+          // slots of query qi over its four lanes (rows g4 of 16 lanes):
+          // exclusive prefix and total of c across the rows, by a 16-lane
+          // and a 32-lane permute (no atomics, no memory)
+          const auto r16 = __builtin_amdgcn_permlane16_swap(uint32_t(c), uint32_t(c), false, false);
+          const int lo = int(r16[0]), hi = int(r16[1]);  // c of rows g4 & ~1 and g4 | 1
+          const auto r32 = __builtin_amdgcn_permlane32_swap(uint32_t(lo + hi), uint32_t(lo + hi), false, false);
+          const int s01 = int(r32[0]), s23 = int(r32[1]);  // c of rows 0 + 1 and 2 + 3
+          int pos = cnt[t] + ((g4 & 1) ? lo : 0) + ((g4 & 2) ? s01 : 0);
+          cnt[t] += s01 + s23;
+          uint64_t* qbuf = bufs + qi * CAP;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (p[r]) qbuf[pos++] = make_key(fmaxf(acc[t][r], 0.0f), int32_t(jb + r));
-          }
+          for (int r = 0; r < 4; ++r)
+            if (p[r]) qbuf[pos++] = make_key(fmaxf(acc[t][r], 0.0f), int32_t(jb + r));
         }
       }
     }
-    // compaction of queries that could overflow in the next tile (lane l
-    // speaks for query l of the wave)
-    const int cl = cnt_s[w * 64 + lane];
-    uint64_t need = __ballot(cl > CAP - B_TJ);
+    // compaction of queries that could overflow in the next tile; lanes
+    // 0..15 speak for queries 16 t + lane
+    uint64_t need = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) need |= (__ballot(cnt[t] > CAP - B_TJ) & 0xFFFFull) << (16 * t);
     while (need) {
       const int r = __ffsll((unsigned long long)need) - 1;
       need &= need - 1;
+      const int t = r >> 4, q = r & 15;
+      const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], q);
       float nt;
-      const int nc = compact_row<EPL>(bufs + (qbase + r) * CAP, __builtin_amdgcn_readlane(cl, r), ncand, CAP - B_TJ,
-                                      nt, hist_s[w]);
-      if (lane == 0) cnt_s[w * 64 + r] = nc;
+      const int nc = compact_row<EPL>(bufs + (qbase + r) * CAP, c, ncand, CAP - B_TJ, nt, hist_s[w]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t == (r >> 4) && q16 == (r & 15)) tau[t] = nt;
+      for (int tt = 0; tt < 4; ++tt)
+        if (tt == t && q16 == q) {
+          cnt[tt] = nc;
+          tau[tt] = nt;
+        }
     }
     buf ^= 1;
   }
   for (int r = 0; r < 64; ++r) {
     const int64_t qi = qbase + r;
     if (qi >= n) break;
-    emit_row<EPL>(bufs + qi * CAP, cnt_s[w * 64 + r], ncand, cand + qi * ncand, nullptr);
+    const int t = r >> 4;
+    const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], r & 15);
+    emit_row<EPL>(bufs + qi * CAP, c, ncand, cand + qi * ncand, nullptr);
   }
 }
 
 // Re-rank: one wave per row; FP32 direct differences (same arithmetic as the
-// FP32 path) of the row's candidates, sorted by (d, j); best k written.
+// FP32 path: squares accumulated in dimension order) of the row's
+// candidates, sorted by (d, j); best k written.  The query row is read with
+// uniform (scalar) loads; each lane issues all loads of a candidate row
+// before the arithmetic (d <= DMAX).
+template <int DMAX>
 __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X, int64_t n, int d,
                                                      const int32_t* __restrict__ cand, int ncand, int k,
                                                      int32_t* __restrict__ out_idx, float* __restrict__ out_d2) {
   const int lane = lane_id();
-  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t row = int64_t(__builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6)));
   if (row >= n) return;
-  const float* xi = X + row * d;
+  float xi[DMAX];
+#pragma unroll
+  for (int c = 0; c < DMAX; ++c) xi[c] = c < d ? X[row * d + c] : 0.0f;
   uint64_t v[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -471,12 +489,18 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X
     const int32_t j = e < ncand ? cand[row * ncand + e] : -1;
     if (j >= 0 && j < n) {  // a row short of candidates (non-finite input) holds -1
       const float* xj = X + int64_t(j) * d;
-      float s = 0.0f;
-      for (int c = 0; c < d; ++c) {
-        const float u = xi[c] - xj[c];
-        s = __builtin_fmaf(u, u, s);
+      float xv[DMAX];
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) xv[c] = c < d ? xj[c] : 0.0f;
+      float s2 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) {
+        if (c < d) {
+          const float u = xi[c] - xv[c];
+          s2 = __builtin_fmaf(u, u, s2);
+        }
       }
-      v[t] = make_key(s, j);
+      v[t] = make_key(s2, j);
     }
   }
   wave_sort<4>(v);
@@ -543,8 +567,8 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   hipLaunchKernelGGL(knn_bf16_kernel<8>, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
                      reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), n, n_cand, bufs, cand);
   TSNE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(rerank_kernel, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, cand, n_cand, k, nbr_idx,
-                     nbr_d2);
+  hipLaunchKernelGGL(rerank_kernel<TSNE_MAX_D_BF16>, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, cand,
+                     n_cand, k, nbr_idx, nbr_d2);
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
 }
