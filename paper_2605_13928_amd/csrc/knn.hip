@@ -16,6 +16,9 @@
 // new threshold.  The true k best always satisfy d <= tau, so nothing is
 // lost; ties at tau are kept and resolved by index in the final sort (a
 // wave-wide bitonic sort of the (d, j) keys).
+#include <cfloat>
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace tsne {
@@ -284,17 +287,24 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
 constexpr uint16_t BF16_ONE = 0x3F80;
+constexpr uint16_t BF16_INF = 0x7F80;
 
 // One wave per row.  Query row:     [x~ (d), nh, nm, nl, 1, 1, 1, 0 ...]
 //                   candidate row:  [-2 x~ (d), 1, 1, 1, nh, nm, nl, 0 ...]
 // so that <query_i, candidate_j> = |x~_i|^2 + |x~_j|^2 - 2 <x~_i, x~_j>, the
 // squared distance of the rounded points; |x~|^2 (FP32) is carried as the
-// sum nh + nm + nl of three bf16 parts.
+// sum nh + nm + nl of three bf16 parts.  Candidate row n is a point at
+// infinite distance from every query ([0 ..., inf at d + 3, 0 ...]): the
+// tiles past the last point are filled with it, so they need no bounds test.
 __global__ __launch_bounds__(256) void bf16_prep_kernel(const float* __restrict__ X, int64_t n, int d,
                                                         uint16_t* __restrict__ Xq, uint16_t* __restrict__ Xc) {
   const int lane = lane_id();
   const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;
+  if (row > n) return;
+  if (row == n) {
+    Xc[row * 64 + lane] = lane == d + 3 ? BF16_INF : uint16_t(0);
+    return;
+  }
   const bool has = lane < d;
   const uint16_t h = has ? bf16_rne(X[row * d + lane]) : uint16_t(0);
   const float xr = bf16_to_f(h);
@@ -334,9 +344,13 @@ __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r 
 // Block = 4 waves x 64 queries.  Lane l works on queries 16 t + (l % 16),
 // t = 0..3, of its wave and, per 16-candidate subtile, on candidates
 // 4 (l / 16) .. + 3 (the MFMA C layout).  A query's threshold and buffer
-// count are held (identically) by its four lanes.
+// count are held (identically) by its four lanes.  Four blocks fit a CU
+// (at most 128 VGPRs; the selection is bound by memory instructions, so
+// resident waves count more than the few registers the compiler then
+// spills outside the append path), and 1024 resident blocks cover 262144
+// queries in one round.
 template <int EPL>
-__global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
+__global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
                                                        int64_t n, int ncand, uint64_t* __restrict__ bufs,
                                                        int32_t* __restrict__ cand) {
   constexpr int CAP = 64 * EPL;
@@ -360,82 +374,89 @@ __global__ __launch_bounds__(256, 3) void knn_bf16_kernel(const uint4* __restric
       if (qi < n) v = Xq[qi * 8 + s * 4 + g4];
       bq[t][s] = __builtin_bit_cast(bf16x8_t, v);
     }
-    tau[t] = qi < n ? INFINITY : -INFINITY;  // queries past n never accept
+    // queries past n never accept; the others accept any finite distance
+    // until their buffer is first compacted (the padding rows are infinite)
+    tau[t] = qi < n ? FLT_MAX : -INFINITY;
   }
-  // prefetch tile 0
-  uint4 nxt[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int u = tid + 256 * h;
-    const int64_t g = u >> 3;
-    nxt[h] = g < n ? Xc[g * 8 + (u & 7)] : make_uint4(0, 0, 0, 0);
-  }
-  int buf = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += B_TJ) {
+  // Tiles go from global memory straight to LDS (global_load_lds_dwordx4:
+  // lane l of a wave writes the 16 bytes at the wave's LDS base + 16 l), so
+  // the swizzle is applied on the global side: LDS slot u holds chunk
+  // (u % 8) ^ (row % 8) of row u / 8.  Rows past n read the infinite row n.
+  auto load_tile = [&](int64_t c0, uint4* dst) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int u = tid + 256 * h;
-      tile[buf][tile_slot(u >> 3, u & 7)] = nxt[h];
+      const int r = u >> 3;
+      const int64_t g = c0 + r;
+      const uint4* src = Xc + (g < n ? g : n) * 8 + ((u & 7) ^ (r & 7));
+      __builtin_amdgcn_global_load_lds(src, dst + (u & ~63), 16, 0, 0);
     }
-    __syncthreads();
+  };
+  load_tile(0, tile[0]);
+  int buf = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += B_TJ) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the tile has landed
+    __syncthreads();                // ... and every wave's; the other buffer is free
     // fetch the next tile while this one is consumed
-    if (c0 + B_TJ < n) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int u = tid + 256 * h;
-        const int64_t g = c0 + B_TJ + (u >> 3);
-        nxt[h] = g < n ? Xc[g * 8 + (u & 7)] : make_uint4(0, 0, 0, 0);
-      }
-    }
+    if (c0 + B_TJ < n) load_tile(c0 + B_TJ, tile[buf ^ 1]);
     const uint4* tl = tile[buf];
-    const bool edge = (c0 + B_TJ > n) || (c0 < qblock + 256 && qblock < c0 + B_TJ);
+    // tiles that hold some of this block's queries exclude the self pairs;
+    // the others need only the threshold test
+    auto sweep = [&](auto edge_c) {
+      constexpr bool EDGE = decltype(edge_c)::value;
 #pragma unroll
-    for (int sub = 0; sub < B_TJ / 16; ++sub) {
-      const int rloc = sub * 16 + q16;
-      const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, tl[tile_slot(rloc, g4)]);
-      const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, tl[tile_slot(rloc, 4 + g4)]);
-      floatx4_t acc[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        acc[t] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bq[t][0], acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bq[t][1], acc[t], 0, 0, 0);
-      }
-      // acc[t][r] = distance(query qbase + 16 t + q16, candidate c0 + 16 sub + 4 g4 + r)
-      bool any = false;
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) any |= acc[t][r] <= tau[t];
-      if (__ballot(any)) {
-        const int64_t jb = c0 + sub * 16 + 4 * g4;
+      for (int sub = 0; sub < B_TJ / 16; ++sub) {
+        const int rloc = sub * 16 + q16;
+        const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, tl[tile_slot(rloc, g4)]);
+        const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, tl[tile_slot(rloc, 4 + g4)]);
+        floatx4_t acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const int64_t qi = qbase + t * 16 + q16;
-          bool p[4];
-          int c = 0;
+          acc[t] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bq[t][0], acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bq[t][1], acc[t], 0, 0, 0);
+        }
+        // acc[t][r] = distance(query qbase + 16 t + q16, candidate c0 + 16 sub + 4 g4 + r)
+        bool any = false;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            p[r] = acc[t][r] <= tau[t] && (!edge || (jb + r < n && jb + r != qi));
-            c += int(p[r]);
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) any |= acc[t][r] <= tau[t];
+        if (__ballot(any)) {
+          const int64_t jb = c0 + sub * 16 + 4 * g4;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int64_t qi = qbase + t * 16 + q16;
+            bool p[4];
+            int c = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              p[r] = acc[t][r] <= tau[t] && (!EDGE || jb + r != qi);
+              c += int(p[r]);
+            }
+            if (__ballot(c != 0) == 0) continue;
+            // slots of query qi over its four lanes (rows g4 of 16 lanes):
+            // exclusive prefix and total of c across the rows, by a 16-lane
+            // and a 32-lane permute (no atomics, no memory)
+            const auto r16 = __builtin_amdgcn_permlane16_swap(uint32_t(c), uint32_t(c), false, false);
+            const int lo = int(r16[0]), hi = int(r16[1]);  // c of rows g4 & ~1 and g4 | 1
+            const auto r32 = __builtin_amdgcn_permlane32_swap(uint32_t(lo + hi), uint32_t(lo + hi), false, false);
+            const int s01 = int(r32[0]), s23 = int(r32[1]);  // c of rows 0 + 1 and 2 + 3
+            int pos = cnt[t] + ((g4 & 1) ? lo : 0) + ((g4 & 2) ? s01 : 0);
+            cnt[t] += s01 + s23;
+            // the buffers of queries qbase + 16 t ..: a wave-uniform base and
+            // a small per-lane offset (no 64-bit pointer per query and t)
+            uint64_t* tbuf = bufs + (qbase + t * 16) * CAP;
+            const int lo_off = q16 * CAP;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (p[r]) tbuf[lo_off + pos++] = make_key(fmaxf(acc[t][r], 0.0f), int32_t(jb + r));
           }
-          if (__ballot(c != 0) == 0) continue;
-          // slots of query qi over its four lanes (rows g4 of 16 lanes):
-          // exclusive prefix and total of c across the rows, by a 16-lane
-          // and a 32-lane permute (no atomics, no memory)
-          const auto r16 = __builtin_amdgcn_permlane16_swap(uint32_t(c), uint32_t(c), false, false);
-          const int lo = int(r16[0]), hi = int(r16[1]);  // c of rows g4 & ~1 and g4 | 1
-          const auto r32 = __builtin_amdgcn_permlane32_swap(uint32_t(lo + hi), uint32_t(lo + hi), false, false);
-          const int s01 = int(r32[0]), s23 = int(r32[1]);  // c of rows 0 + 1 and 2 + 3
-          int pos = cnt[t] + ((g4 & 1) ? lo : 0) + ((g4 & 2) ? s01 : 0);
-          cnt[t] += s01 + s23;
-          uint64_t* qbuf = bufs + qi * CAP;
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (p[r]) qbuf[pos++] = make_key(fmaxf(acc[t][r], 0.0f), int32_t(jb + r));
         }
       }
-    }
+    };
+    if (c0 < qblock + 256 && qblock < c0 + B_TJ) sweep(std::true_type{});
+    else sweep(std::false_type{});
     // compaction of queries that could overflow in the next tile; lanes
     // 0..15 speak for queries 16 t + lane
     uint64_t need = 0;
@@ -528,7 +549,7 @@ struct KnnLayout {
       L.epl = 8;  // capacity 512, headroom 64 per tile
       L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * 512);
       L.o_xq = c.take(sizeof(uint16_t) * size_t(n) * 64);
-      L.o_xc = c.take(sizeof(uint16_t) * size_t(n) * 64);
+      L.o_xc = c.take(sizeof(uint16_t) * size_t(n + 1) * 64);  // + the infinite row
       L.o_cand = c.take(sizeof(int32_t) * size_t(n) * size_t(ncand));
     }
     L.bytes = c.off;
@@ -562,7 +583,7 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   uint16_t* Xq = reinterpret_cast<uint16_t*>(ws + L.o_xq);
   uint16_t* Xc = reinterpret_cast<uint16_t*>(ws + L.o_xc);
   int32_t* cand = reinterpret_cast<int32_t*>(ws + L.o_cand);
-  hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, Xq, Xc);
+  hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(n + 1, 4))), dim3(256), 0, s, X, n, d, Xq, Xc);
   TSNE_CHECK_LAUNCH();
   hipLaunchKernelGGL(knn_bf16_kernel<8>, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
                      reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), n, n_cand, bufs, cand);

@@ -96,6 +96,20 @@ def test_knn_bf16_small(dev, n):
     say("bf16 agreement", n, raw, adj)
 
 
+@pytest.mark.parametrize("n,d,k", [(3, 2, 1), (65, 3, 5), (333, 58, 20), (1000, 17, 64)])
+def test_knn_bf16_shapes(dev, n, d, k):
+    # dimensions from 2 to the largest the BF16 layout takes (58: the six
+    # norm slots end at element 63), ragged n (partial candidate tiles read
+    # the padding row, partial query blocks hold queries past n)
+    say("knn bf16 shape", n, d, k)
+    X = (np.random.default_rng(n + d).standard_normal((n, d)) * 3).astype(np.float32)
+    nc = min(2 * k, n - 1)
+    oi, od = oracle.knn(X, k)
+    gi, gd = gpu_knn(dev, X, k, "bf16", n_cand=nc)
+    raw, adj = check_knn(X, np.arange(n), gi, gd, oi, od, min_agree=0.99)
+    say("bf16 agreement", n, d, raw, adj)
+
+
 def test_knn_bf16_candidates_are_rounded_point_neighbours(dev):
     # With n_cand = k the re-rank only reorders, so the set is the BF16
     # candidate set itself: the k nearest of the bf16-rounded points, which
