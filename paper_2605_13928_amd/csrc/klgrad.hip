@@ -33,7 +33,7 @@ namespace tsne {
 constexpr int FIN_ROWS = 16;
 constexpr int FIN_EPT = 8;
 constexpr int FIN_CHUNK = 256 * FIN_EPT;
-constexpr int FIN_PRE = 4;  // partial slices per thread loaded up front
+constexpr int FIN_PRE = 5;  // partial slices per thread loaded up front (all of them for ns <= 80)
 
 template <bool STEP, bool ATTP>
 __global__ __launch_bounds__(256) void finalize_tsne_kernel(
@@ -64,6 +64,13 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     const bool ok = prow < n && k < ns;
     rpv[u] = ok ? Rpart[part_index(prow, k, ns, n, grouped)] : make_float2(0.0f, 0.0f);
     apv[u] = (ATTP && ok) ? Apart[part_index(prow, k, ns, n, grouped)] : make_float2(0.0f, 0.0f);
+  }
+  // the stepped rows' state (in flight while the partials are summed)
+  float2 sy = make_float2(0.0f, 0.0f), su = sy, sg = sy;
+  if (STEP && tid < FIN_ROWS && r0 + tid < n) {
+    sy = Y[r0 + tid];
+    su = st.U[r0 + tid];
+    sg = st.G[r0 + tid];
   }
   const double zt = zblock_thread_sum(Zblock, nZ);
   __syncthreads();
@@ -117,14 +124,6 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
       ay += c.y;
     }
     __syncthreads();
-  }
-
-  // the stepped rows' state (in flight while the partials are summed)
-  float2 sy = make_float2(0.0f, 0.0f), su = sy, sg = sy;
-  if (STEP && tid < FIN_ROWS && r0 + tid < n) {
-    sy = Y[r0 + tid];
-    su = st.U[r0 + tid];
-    sg = st.G[r0 + tid];
   }
 
   // --- repulsion partials: slices g, g + 16, ... in order ------------------

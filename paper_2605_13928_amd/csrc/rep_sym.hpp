@@ -262,16 +262,17 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
   const int64_t P = gridDim.x;
   float* myj = jacc + w * NC * S;
 
-  // points of job q into registers (thread tid holds points tid + 256 k)
+  // points of job q into registers (thread tid holds points tid + 256 k),
+  // and the job's superblock pair (fs, ft)
   float2 pi[PF], pj[PF];
+  int64_t fs = 0, ft = 0;
   auto fetch = [&](int64_t q) {
-    int64_t s, t;
-    job_pair(q, ns, s, t);
+    job_pair(q, ns, fs, ft);
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int u = tid + 256 * k;
-      pi[k] = load_point(Y, s * S + u, n);
-      pj[k] = load_point(Y, t * S + u, n);
+      pi[k] = load_point(Y, fs * S + u, n);
+      pj[k] = load_point(Y, ft * S + u, n);
     }
   };
   // attraction entries: the next job's range and first two entries per
@@ -328,8 +329,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
     for (int u = tid; u < 4 * S; u += 256) aacc[u] = 0ull;
   double zsum = 0.0;
   for (; q < njobs; q += P) {
-    int64_t s, t;
-    job_pair(q, ns, s, t);
+    const int64_t s = fs, t = ft;  // job q, decoded by its fetch
     const bool diag_sb = s == t;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
