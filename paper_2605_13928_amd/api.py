@@ -171,6 +171,30 @@ def kl_grad(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, grad: torch.
     return grad, Z, kl, Zrow
 
 
+def kl_grad_fft(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, n_interp: int = 3, min_boxes: int = 50,
+                max_box_width: float = 1.0, max_fft: int = 2048, grad: torch.Tensor | None = None,
+                want_Z: bool = False, want_kl: bool = False, ws: Workspace | None = None):
+    """t-SNE gradient with the repulsion and Z by FFT-accelerated interpolation
+    (tsne_kl_grad_fft).  Returns (grad [n, 2] f32, Z f64[1] or None, KL f64[1] or None)."""
+    _req(Y, "Y", torch.float32)
+    n = Y.shape[0]
+    if Y.shape != (n, 2) or P.n != n:
+        raise ValueError("Y must be [n, 2] matching P")
+    dev = Y.device
+    if grad is None:
+        grad = torch.empty_like(Y)
+    else:
+        _req(grad, "grad", torch.float32, (n, 2))
+    Z = torch.empty(1, dtype=torch.float64, device=dev) if want_Z else None
+    kl = torch.empty(1, dtype=torch.float64, device=dev) if want_kl else None
+    L = _lib.load()
+    _run_with_workspace("tsne_kl_grad_fft", L.tsne_kl_grad_fft,
+                        (_ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val), float(exaggeration), int(n_interp),
+                         int(min_boxes), float(max_box_width), int(max_fft), _ptr(grad), _ptr(Z), _ptr(kl)),
+                        (_stream(dev),), dev, ws, key=("kl_grad_fft", n, int(max_fft)))
+    return grad, Z, kl
+
+
 def step(Y, update, gains, grad, lr: float, momentum: float, gain_inc: float = 0.2, gain_dec: float = 0.8,
          min_gain: float = 0.01):
     """In-place momentum + gains step on [n, 2] float32 tensors."""

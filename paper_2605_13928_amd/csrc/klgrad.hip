@@ -243,6 +243,26 @@ __global__ __launch_bounds__(256) void kl_reduce_kernel(const double* __restrict
   if (threadIdx.x == 0) *kl_out = a + b + c * log(Z);
 }
 
+size_t finalize_kl_bytes(int64_t n) { return sizeof(double) * 3 * size_t(ceil_div(n, FIN_ROWS)); }
+
+int finalize_csr_launch(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
+                        float alpha, const float* R, const double* Zblock, int64_t nZ, float* grad, double* Z,
+                        double* kl, double* klpart, hipStream_t s) {
+  const int64_t nfin = ceil_div(n, FIN_ROWS);
+  double* kp = kl ? klpart : nullptr;
+  hipLaunchKernelGGL((finalize_tsne_kernel<false, false>), dim3(unsigned(nfin)), dim3(256), 0, s,
+                     reinterpret_cast<const float2*>(Y), n, row_ptr, col, val, alpha,
+                     reinterpret_cast<const float2*>(R), static_cast<const float*>(nullptr),
+                     static_cast<const float2*>(nullptr), int64_t(1), false, Zblock, nZ,
+                     reinterpret_cast<float2*>(grad), static_cast<double*>(nullptr), Z, kp, FusedStep{});
+  TSNE_CHECK_LAUNCH();
+  if (kl) {
+    hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, kp, nfin, Zblock, nZ, kl);
+    TSNE_CHECK_LAUNCH();
+  }
+  return TSNE_OK;
+}
+
 KlGradPlan klgrad_plan(int64_t n, bool with_att) {
   KlGradPlan L;
   L.g = SymGrid::make(n);

@@ -60,6 +60,15 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
                   hipStream_t s, const FusedStep* step = nullptr, hipEvent_t after_repulsion = nullptr,
                   const AttList* att = nullptr);
 
+// Finalize of a gradient whose repulsion R (one float2 per point) and Z
+// block partials (Z = their sum, in index order) were computed elsewhere:
+// attraction over the CSR rows, g = 4 (alpha A - R / Z), optional Z and KL
+// outputs.  klpart: finalize_kl_bytes(n) of workspace (used when kl).
+size_t finalize_kl_bytes(int64_t n);
+int finalize_csr_launch(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
+                        float alpha, const float* R, const double* Zblock, int64_t nZ, float* grad, double* Z,
+                        double* kl, double* klpart, hipStream_t s);
+
 // Enqueue one optimiser step (arguments as tsne_step, validated).
 int step_launch(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr, float momentum,
                 float gain_inc, float gain_dec, float min_gain, hipStream_t s);

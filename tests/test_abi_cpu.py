@@ -94,6 +94,23 @@ def test_invalid_arguments_rejected(L):
     assert ws_query(L.tsne_kl_grad, fake, 1, fake, fake, fake, C.c_float(1.0), fake, NULL, NULL, NULL)[0] == IA
     assert ws_query(L.tsne_kl_grad, fake, 10, fake, fake, fake, C.c_float(0.0), fake, NULL, NULL, NULL)[0] == IA
     assert ws_query(L.tsne_kl_grad, fake, 10, fake, fake, fake, C.c_float(1.0), NULL, NULL, NULL, NULL)[0] == IA
+    # interpolated gradient: n_interp 2..5, min_boxes >= 1, box width > 0,
+    # max_fft a power of two in [64, 4096] with 2 p min_boxes <= max_fft
+    fg = L.tsne_kl_grad_fft
+
+    def fq(n=10, p=3, mb=50, w=1.0, mf=2048, g=fake):
+        return ws_query(fg, fake, n, fake, fake, fake, C.c_float(1.0), p, mb, C.c_float(w), mf, g, NULL, NULL)
+
+    rc, need = fq()
+    plane = 2048 * 2048
+    assert rc == 0 and need >= 5 * 16 * plane + 3 * 8 * 1024 * 1024
+    assert fq(mf=4096)[1] > 3 * need
+    assert fq(n=1)[0] == IA and fq(g=NULL)[0] == IA
+    assert fq(p=1)[0] == IA and fq(p=6)[0] == IA and fq(mb=0)[0] == IA
+    assert fq(w=0.0)[0] == IA and fq(w=float("inf"))[0] == IA
+    assert fq(mf=32)[0] == IA and fq(mf=8192)[0] == IA and fq(mf=1000)[0] == IA
+    assert fq(p=5, mb=50, mf=256)[0] == IA  # 2 p min_boxes > max_fft
+    assert fq(p=2, mb=16, mf=64)[0] == 0
     st = L.tsne_step
     assert st(NULL, fake, fake, fake, 10, C.c_float(200), C.c_float(0.5), C.c_float(0.2), C.c_float(0.8),
               C.c_float(0.01), NULL) == IA
