@@ -194,7 +194,8 @@ int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_
  * box's nodes with tensor Lagrange weights; the node potentials of the
  * kernels 1 / (1 + r^2) and its square are circular convolutions of the
  * zero-padded node grids, done as 2-D FFTs in FP64 of size F = the smallest
- * power of two >= max(64, 2 p B); each point interpolates them back:
+ * power of two >= max(64, 2 p B) (the kernels are even, so two real grids
+ * share each complex transform); each point interpolates them back:
  *   R_i = (y_i - c) phi2_i - phi3_i,  Z = sum_i phi1_i - n,
  *   g_i = 4 (alpha A_i - R_i / Z).
  * The error falls as h^p (third order for p = 3); box side 1 (the default
@@ -209,7 +210,7 @@ int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_
  *   max_box_width  upper bound of h while B < max_fft / (2 p) (> 0; 1.0).
  *   max_fft        largest F, a power of two in [64, 4096] with
  *                  2 p min_boxes <= max_fft (2048); the workspace grows as
- *                  80 max_fft^2 bytes plus 6 max_fft^2 for the node sums.
+ *                  48 max_fft^2 bytes plus 6 max_fft^2 for the node sums.
  */
 int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                      float exaggeration, int32_t n_interp, int32_t min_boxes, float max_box_width, int32_t max_fft,

@@ -14,13 +14,17 @@
 //                                weights to the p x p nodes of its box, as
 //                                64-bit fixed-point integer atomics (exact
 //                                and order-independent: deterministic).
-//   load_kernel                  the three charge grids and the two kernel
-//                                grids K1 = 1 / (1 + r^2), K2 = K1^2 at the
-//                                node offsets, zero-padded / wrapped to F x F
-//                                (circular convolution = linear for F >= 2N).
+//   load_kernel                  three complex F x F grids, zero-padded /
+//                                wrapped (circular convolution = linear for
+//                                F >= 2N): W0, W1 + i W2, and K1 + i K2 with
+//                                K1 = 1 / (1 + r^2), K2 = K1^2 at the node
+//                                offsets.
 //   2-D FFT (FP64)               row FFTs in LDS, an in-place transpose, row
-//                                FFTs again; products K1 W0, K2 W0, K2 W1,
-//                                K2 W2; the inverse the same way back.
+//                                FFTs again.  The kernels are even, so their
+//                                spectra are real: FFT(W0) (K1^ + i K2^)
+//                                transforms back to phi1 + i phi2 and
+//                                (W1^ + i W2^) K2^ to phi3x + i phi3y -- three
+//                                forward and two inverse transforms.
 //   gather_kernel                each point interpolates the four node
 //                                potentials: R_i = z_i phi2 - (phi3x, phi3y),
 //                                Z = sum_i phi1_i - n (the j = i terms).
@@ -179,8 +183,9 @@ __global__ __launch_bounds__(256) void fi_spread_kernel(const float2* __restrict
   }
 }
 
-// The five F x F complex grids: charges W0..W2 (zero-padded) and kernels
-// K1, K2 at the wrapped node offsets.  Buffer ch at Cg + ch F^2 (row-major).
+// The three F x F complex grids: W0, W1 + i W2 (zero-padded) and K1 + i K2
+// at the wrapped node offsets.  Plane ch at Cg + ch * plane, row-major with
+// row stride F.
 __global__ __launch_bounds__(256) void fi_load_kernel(const unsigned long long* __restrict__ G,
                                                       const FiParams* __restrict__ gp, int p,
                                                       double2* __restrict__ Cg, int64_t plane) {
@@ -205,10 +210,8 @@ __global__ __launch_bounds__(256) void fi_load_kernel(const unsigned long long* 
       k1 = 1.0 / (1.0 + dx * dx + dy * dy);
     }
     Cg[t] = make_double2(w0, 0.0);
-    Cg[plane + t] = make_double2(w1, 0.0);
-    Cg[2 * plane + t] = make_double2(w2, 0.0);
-    Cg[3 * plane + t] = make_double2(k1, 0.0);
-    Cg[4 * plane + t] = make_double2(k1 * k1, 0.0);
+    Cg[plane + t] = make_double2(w1, w2);
+    Cg[2 * plane + t] = make_double2(k1, k1 * k1);
   }
 }
 
@@ -277,25 +280,22 @@ __global__ __launch_bounds__(256) void fi_transpose_kernel(double2* __restrict__
   }
 }
 
-// Spectra: plane 3 <- W0 K1, plane 0 <- W0 K2, plane 1 <- W1 K2, plane 2 <- W2 K2.
+// Spectra: plane 0 <- W0^ (K1^ + i K2^), plane 1 <- (W1^ + i W2^) K2^, with
+// K2^ = Im of plane 2 (K1^, K2^ real).
 __global__ __launch_bounds__(256) void fi_mult_kernel(double2* __restrict__ Cg, int64_t plane,
                                                       const FiParams* __restrict__ gp) {
   const int64_t FF = int64_t(gp->F) * gp->F;
-  auto mul = [](double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); };
   for (int64_t t = gtid(); t < FF; t += int64_t(gridDim.x) * 256) {
-    const double2 w0 = Cg[t], w1 = Cg[plane + t], w2 = Cg[2 * plane + t];
-    const double2 k1 = Cg[3 * plane + t], k2 = Cg[4 * plane + t];
-    Cg[3 * plane + t] = mul(w0, k1);
-    Cg[t] = mul(w0, k2);
-    Cg[plane + t] = mul(w1, k2);
-    Cg[2 * plane + t] = mul(w2, k2);
+    const double2 w0 = Cg[t], w12 = Cg[plane + t], k = Cg[2 * plane + t];
+    Cg[t] = make_double2(w0.x * k.x - w0.y * k.y, w0.x * k.y + w0.y * k.x);
+    Cg[plane + t] = make_double2(w12.x * k.y, w12.y * k.y);
   }
 }
 
 // --- gather ------------------------------------------------------------
 
-// Point values of the potentials (real parts / F^2): phi1 from plane 3,
-// phi2 from plane 0, phi3 from planes 1 and 2.  R_i = z_i phi2 - phi3;
+// Point values of the potentials (divided by F^2): phi1 + i phi2 from
+// plane 0, phi3x + i phi3y from plane 1.  R_i = z_i phi2 - phi3;
 // Z partials per block in FP64 (block 0 also subtracts the n self terms).
 template <int P>
 __global__ __launch_bounds__(256) void fi_gather_kernel(const float2* __restrict__ Y, int64_t n,
@@ -318,10 +318,11 @@ __global__ __launch_bounds__(256) void fi_gather_kernel(const float2* __restrict
       for (int ky = 0; ky < P; ++ky) {
         const double w = Lx[kx] * Ly[ky];
         const int64_t t = int64_t(P * bx + kx) * g.F + (P * by + ky);
-        f1 += w * Cg[3 * plane + t].x;
-        f2 += w * Cg[t].x;
-        f3x += w * Cg[plane + t].x;
-        f3y += w * Cg[2 * plane + t].x;
+        const double2 a = Cg[t], b = Cg[plane + t];
+        f1 += w * a.x;
+        f2 += w * a.y;
+        f3x += w * b.x;
+        f3y += w * b.y;
       }
     }
     f1 *= norm;
@@ -349,7 +350,7 @@ FiPlan fi_plan(int64_t n, int max_fft) {
   L.o_part = c.take(sizeof(float) * 2 * FI_GRID);
   L.o_par = c.take(sizeof(FiParams));
   L.o_G = c.take(sizeof(unsigned long long) * 3 * size_t(Nmax) * size_t(Nmax));
-  L.o_C = c.take(sizeof(double2) * 5 * size_t(L.plane));
+  L.o_C = c.take(sizeof(double2) * 3 * size_t(L.plane));
   L.o_R = c.take(sizeof(float2) * size_t(n));
   L.o_Zb = c.take(sizeof(double) * FI_GRID);
   L.o_kl = c.take(finalize_kl_bytes(n));
@@ -427,10 +428,10 @@ extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_pt
   if ((rc = fi_points(n_interp, true, Y2, n, par, G, Cg, L.plane, R, Zb, s))) return rc;
   hipLaunchKernelGGL(fi_load_kernel, dim3(4096), dim3(256), 0, s, G, par, n_interp, Cg, L.plane);
   TSNE_CHECK_LAUNCH();
-  if ((rc = fi_fft2(Cg, L.plane, 5, par, max_fft, -1.0, s))) return rc;
+  if ((rc = fi_fft2(Cg, L.plane, 3, par, max_fft, -1.0, s))) return rc;
   hipLaunchKernelGGL(fi_mult_kernel, dim3(4096), dim3(256), 0, s, Cg, L.plane, par);
   TSNE_CHECK_LAUNCH();
-  if ((rc = fi_fft2(Cg, L.plane, 4, par, max_fft, 1.0, s))) return rc;
+  if ((rc = fi_fft2(Cg, L.plane, 2, par, max_fft, 1.0, s))) return rc;
   if ((rc = fi_points(n_interp, false, Y2, n, par, G, Cg, L.plane, R, Zb, s))) return rc;
   return finalize_csr_launch(Y, n, row_ptr, col, val, exaggeration, reinterpret_cast<const float*>(R), Zb, FI_GRID,
                              grad, Z, kl, klp, s);

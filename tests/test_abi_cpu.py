@@ -103,7 +103,7 @@ def test_invalid_arguments_rejected(L):
 
     rc, need = fq()
     plane = 2048 * 2048
-    assert rc == 0 and need >= 5 * 16 * plane + 3 * 8 * 1024 * 1024
+    assert rc == 0 and need >= 3 * 16 * plane + 3 * 8 * 1024 * 1024
     assert fq(mf=4096)[1] > 3 * need
     assert fq(n=1)[0] == IA and fq(g=NULL)[0] == IA
     assert fq(p=1)[0] == IA and fq(p=6)[0] == IA and fq(mb=0)[0] == IA
