@@ -9,11 +9,14 @@
 //                                local positions (k + 1/2) / p, so N = p B
 //                                equispaced nodes (spacing h / p) per axis;
 //                                FFT size F = smallest power of two >= 2 N.
-//   spread_kernel                each point adds its charges 1, z_x, z_y
-//                                (z = y - centre) times the tensor Lagrange
-//                                weights to the p x p nodes of its box, as
-//                                64-bit fixed-point integer atomics (exact
-//                                and order-independent: deterministic).
+//   count / scan / scatter       the points sorted by box (counting sort).
+//   accum_kernel                 one thread per box sums its points' charges
+//                                1, z_x, z_y (z = y - centre) times the
+//                                tensor Lagrange weights into the box's
+//                                p x p nodes, in 64-bit fixed point (exact,
+//                                so independent of the order the scatter
+//                                leaves: deterministic), and writes them;
+//                                every node belongs to exactly one box.
 //   load_kernel                  three complex F x F grids, zero-padded /
 //                                wrapped (circular convolution = linear for
 //                                F >= 2N): W0, W1 + i W2, and K1 + i K2 with
@@ -35,6 +38,7 @@
 
 #include "common.hpp"
 #include "klgrad.hpp"
+#include "scan.hpp"
 
 namespace tsne {
 
@@ -150,34 +154,77 @@ __device__ __forceinline__ int fi_weights(float y, const FiParams& g, double (&L
 
 // --- spread ------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void fi_clear_kernel(unsigned long long* __restrict__ g,
-                                                       const FiParams* __restrict__ gp) {
-  const int64_t cnt = 3 * int64_t(gp->N) * gp->N;
-  for (int64_t t = gtid(); t < cnt; t += int64_t(gridDim.x) * 256) g[t] = 0ull;
+// Box of a point (the same clamped FP64 floor as fi_weights).
+__device__ __forceinline__ int fi_box(float y, const FiParams& g) {
+  const double t = (double(y) - g.lo) / g.h;
+  return int(fmin(fmax(floor(t), 0.0), double(g.B - 1)));
 }
 
-// Grids: channel c at G + c N^2, node (gx, gy) at gx N + gy.
-template <int P>
-__global__ __launch_bounds__(256) void fi_spread_kernel(const float2* __restrict__ Y, int64_t n,
-                                                        const FiParams* __restrict__ gp,
-                                                        unsigned long long* __restrict__ G) {
+__global__ __launch_bounds__(256) void fi_count_kernel(const float2* __restrict__ Y, int64_t n,
+                                                       const FiParams* __restrict__ gp, int* __restrict__ cnt) {
   const FiParams g = *gp;
-  const int64_t NN = int64_t(g.N) * g.N;
   for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * 256) {
     const float2 y = Y[i];
-    double Lx[P], Ly[P];
-    const int bx = fi_weights<P>(y.x, g, Lx);
-    const int by = fi_weights<P>(y.y, g, Ly);
-    const double zx = double(y.x) - g.c, zy = double(y.y) - g.c;
+    atomicAdd(&cnt[fi_box(y.x, g) * g.B + fi_box(y.y, g)], 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void fi_scatter_kernel(const float2* __restrict__ Y, int64_t n,
+                                                         const FiParams* __restrict__ gp,
+                                                         const int64_t* __restrict__ off, int* __restrict__ cur,
+                                                         int32_t* __restrict__ order) {
+  const FiParams g = *gp;
+  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * 256) {
+    const float2 y = Y[i];
+    const int b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
+    order[off[b] + atomicAdd(&cur[b], 1)] = int32_t(i);
+  }
+}
+
+// Node sums of box b (thread b < B^2): channel c at G + c N^2, node
+// (gx, gy) at gx N + gy.
+template <int P>
+__global__ __launch_bounds__(256) void fi_accum_kernel(const float2* __restrict__ Y,
+                                                       const FiParams* __restrict__ gp,
+                                                       const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ order,
+                                                       unsigned long long* __restrict__ G) {
+  const FiParams g = *gp;
+  const int64_t nb = int64_t(g.B) * g.B;
+  const int64_t NN = int64_t(g.N) * g.N;
+  for (int64_t b = gtid(); b < nb; b += int64_t(gridDim.x) * 256) {
+    long long acc[3][P][P];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int kx = 0; kx < P; ++kx)
+#pragma unroll
+        for (int ky = 0; ky < P; ++ky) acc[c][kx][ky] = 0;
+    for (int64_t e = off[b]; e < off[b + 1]; ++e) {
+      const float2 y = Y[order[e]];
+      double Lx[P], Ly[P];
+      fi_weights<P>(y.x, g, Lx);
+      fi_weights<P>(y.y, g, Ly);
+      const double zx = double(y.x) - g.c, zy = double(y.y) - g.c;
+#pragma unroll
+      for (int kx = 0; kx < P; ++kx) {
+#pragma unroll
+        for (int ky = 0; ky < P; ++ky) {
+          const double w = Lx[kx] * Ly[ky] * g.scale;
+          acc[0][kx][ky] += __double2ll_rn(w);
+          acc[1][kx][ky] += __double2ll_rn(w * zx);
+          acc[2][kx][ky] += __double2ll_rn(w * zy);
+        }
+      }
+    }
+    const int bx = int(b / g.B), by = int(b % g.B);
 #pragma unroll
     for (int kx = 0; kx < P; ++kx) {
 #pragma unroll
       for (int ky = 0; ky < P; ++ky) {
-        const double w = Lx[kx] * Ly[ky] * g.scale;
         const int64_t node = int64_t(P * bx + kx) * g.N + (P * by + ky);
-        atomicAdd(&G[node], (unsigned long long)__double2ll_rn(w));
-        atomicAdd(&G[NN + node], (unsigned long long)__double2ll_rn(w * zx));
-        atomicAdd(&G[2 * NN + node], (unsigned long long)__double2ll_rn(w * zy));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[c * NN + node] = (unsigned long long)acc[c][kx][ky];
       }
     }
   }
@@ -338,17 +385,24 @@ __global__ __launch_bounds__(256) void fi_gather_kernel(const float2* __restrict
 }
 
 struct FiPlan {
-  size_t o_part, o_par, o_G, o_C, o_R, o_Zb, o_kl, bytes;
-  int64_t plane;
+  size_t o_part, o_par, o_G, o_C, o_R, o_Zb, o_kl, o_cnt, o_cur, o_off, o_bsum, o_ord, bytes;
+  int64_t plane, nbox;  // nbox: boxes of the largest grid (B <= max_fft / 4)
 };
 
 FiPlan fi_plan(int64_t n, int max_fft) {
   FiPlan L;
   Carve c;
   const int64_t Nmax = max_fft / 2;
+  const int64_t Bmax = max_fft / 4;  // p >= 2
   L.plane = int64_t(max_fft) * max_fft;
+  L.nbox = Bmax * Bmax;
   L.o_part = c.take(sizeof(float) * 2 * FI_GRID);
   L.o_par = c.take(sizeof(FiParams));
+  L.o_cnt = c.take(sizeof(int) * size_t(L.nbox));
+  L.o_cur = c.take(sizeof(int) * size_t(L.nbox));
+  L.o_off = c.take(sizeof(int64_t) * size_t(L.nbox + 1));
+  L.o_bsum = c.take(sizeof(int64_t) * (size_t(ceil_div(L.nbox + 1, SCAN_CHUNK)) + 1));
+  L.o_ord = c.take(sizeof(int32_t) * size_t(n));
   L.o_G = c.take(sizeof(unsigned long long) * 3 * size_t(Nmax) * size_t(Nmax));
   L.o_C = c.take(sizeof(double2) * 3 * size_t(L.plane));
   L.o_R = c.take(sizeof(float2) * size_t(n));
@@ -359,22 +413,27 @@ FiPlan fi_plan(int64_t n, int max_fft) {
 }
 
 template <int P>
-int fi_launch_points(bool spread, const float2* Y, int64_t n, const FiParams* par, unsigned long long* G,
-                     const double2* Cg, int64_t plane, float2* R, double* Zb, hipStream_t s) {
-  const dim3 grid(FI_GRID), block(256);
-  if (spread) hipLaunchKernelGGL(fi_spread_kernel<P>, grid, block, 0, s, Y, n, par, G);
-  else hipLaunchKernelGGL(fi_gather_kernel<P>, grid, block, 0, s, Y, n, par, Cg, plane, R, Zb);
+int fi_launch_points(bool spread, const float2* Y, int64_t n, const FiParams* par, const int64_t* off,
+                     const int32_t* order, int64_t nbox, unsigned long long* G, const double2* Cg, int64_t plane,
+                     float2* R, double* Zb, hipStream_t s) {
+  if (spread) {
+    hipLaunchKernelGGL(fi_accum_kernel<P>, dim3(unsigned(ceil_div(nbox, 256))), dim3(256), 0, s, Y, par, off, order,
+                       G);
+  } else {
+    hipLaunchKernelGGL(fi_gather_kernel<P>, dim3(FI_GRID), dim3(256), 0, s, Y, n, par, Cg, plane, R, Zb);
+  }
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
 }
 
-int fi_points(int p, bool spread, const float2* Y, int64_t n, const FiParams* par, unsigned long long* G,
-              const double2* Cg, int64_t plane, float2* R, double* Zb, hipStream_t s) {
+int fi_points(int p, bool spread, const float2* Y, int64_t n, const FiParams* par, const int64_t* off,
+              const int32_t* order, int64_t nbox, unsigned long long* G, const double2* Cg, int64_t plane, float2* R,
+              double* Zb, hipStream_t s) {
   switch (p) {
-    case 2: return fi_launch_points<2>(spread, Y, n, par, G, Cg, plane, R, Zb, s);
-    case 3: return fi_launch_points<3>(spread, Y, n, par, G, Cg, plane, R, Zb, s);
-    case 4: return fi_launch_points<4>(spread, Y, n, par, G, Cg, plane, R, Zb, s);
-    default: return fi_launch_points<5>(spread, Y, n, par, G, Cg, plane, R, Zb, s);
+    case 2: return fi_launch_points<2>(spread, Y, n, par, off, order, nbox, G, Cg, plane, R, Zb, s);
+    case 3: return fi_launch_points<3>(spread, Y, n, par, off, order, nbox, G, Cg, plane, R, Zb, s);
+    case 4: return fi_launch_points<4>(spread, Y, n, par, off, order, nbox, G, Cg, plane, R, Zb, s);
+    default: return fi_launch_points<5>(spread, Y, n, par, off, order, nbox, G, Cg, plane, R, Zb, s);
   }
 }
 
@@ -417,22 +476,34 @@ extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_pt
   float2* R = reinterpret_cast<float2*>(ws + L.o_R);
   double* Zb = reinterpret_cast<double*>(ws + L.o_Zb);
   double* klp = reinterpret_cast<double*>(ws + L.o_kl);
+  int* cnt = reinterpret_cast<int*>(ws + L.o_cnt);
+  int* cur = reinterpret_cast<int*>(ws + L.o_cur);
+  int64_t* off = reinterpret_cast<int64_t*>(ws + L.o_off);
+  int64_t* bsum = reinterpret_cast<int64_t*>(ws + L.o_bsum);
+  int32_t* order = reinterpret_cast<int32_t*>(ws + L.o_ord);
 
   hipLaunchKernelGGL(fi_bbox_kernel, dim3(FI_GRID), dim3(256), 0, s, Y2, n, part);
   TSNE_CHECK_LAUNCH();
   hipLaunchKernelGGL(fi_params_kernel, dim3(1), dim3(256), 0, s, part, FI_GRID, n, n_interp, min_boxes,
                      max_box_width, max_fft, par);
   TSNE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(fi_clear_kernel, dim3(2048), dim3(256), 0, s, G, par);
+  // counting sort of the points by box, then the per-box node sums
+  if ((rc = launch_fill<int>(cnt, L.nbox, 0, s))) return rc;
+  if ((rc = launch_fill<int>(cur, L.nbox, 0, s))) return rc;
+  const dim3 pgrid(unsigned(ceil_div(n, 256) < 4096 ? ceil_div(n, 256) : 4096));
+  hipLaunchKernelGGL(fi_count_kernel, pgrid, dim3(256), 0, s, Y2, n, par, cnt);
   TSNE_CHECK_LAUNCH();
-  if ((rc = fi_points(n_interp, true, Y2, n, par, G, Cg, L.plane, R, Zb, s))) return rc;
+  if ((rc = exclusive_scan<int>(cnt, L.nbox, off, bsum, s))) return rc;
+  hipLaunchKernelGGL(fi_scatter_kernel, pgrid, dim3(256), 0, s, Y2, n, par, off, cur, order);
+  TSNE_CHECK_LAUNCH();
+  if ((rc = fi_points(n_interp, true, Y2, n, par, off, order, L.nbox, G, Cg, L.plane, R, Zb, s))) return rc;
   hipLaunchKernelGGL(fi_load_kernel, dim3(4096), dim3(256), 0, s, G, par, n_interp, Cg, L.plane);
   TSNE_CHECK_LAUNCH();
   if ((rc = fi_fft2(Cg, L.plane, 3, par, max_fft, -1.0, s))) return rc;
   hipLaunchKernelGGL(fi_mult_kernel, dim3(4096), dim3(256), 0, s, Cg, L.plane, par);
   TSNE_CHECK_LAUNCH();
   if ((rc = fi_fft2(Cg, L.plane, 2, par, max_fft, 1.0, s))) return rc;
-  if ((rc = fi_points(n_interp, false, Y2, n, par, G, Cg, L.plane, R, Zb, s))) return rc;
+  if ((rc = fi_points(n_interp, false, Y2, n, par, off, order, L.nbox, G, Cg, L.plane, R, Zb, s))) return rc;
   return finalize_csr_launch(Y, n, row_ptr, col, val, exaggeration, reinterpret_cast<const float*>(R), Zb, FI_GRID,
                              grad, Z, kl, klp, s);
 }
