@@ -9,7 +9,9 @@ which records HIP events (on the stream the kernels are launched on) right
 around every 10th launch of the all-pairs repulsion kernel: they give the
 dominant kernel's average per-launch time for the roofline.  Outside the timed region: the BF16-MFMA vs FP32 kNN build
 comparison, and the CPU-baseline leg (the FP64 oracle timed on a bounded
-sample of the same workload, which also yields the error statistics).
+sample of the same workload, which also yields the error statistics), the
+KL autograd timing, and the interpolated (FFT) gradient timed against the
+exact one at the C5 point count.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 """
@@ -42,6 +44,8 @@ def parse():
                     help="point count of the BF16-vs-FP32 kNN build comparison (C3 shape)")
     ap.add_argument("--autograd-n", type=int, default=50_000,
                     help="point count of the KL autograd forward/backward timing (0: skip)")
+    ap.add_argument("--fft-n", type=int, default=1_000_000,
+                    help="point count of the interpolated-vs-exact gradient comparison (C5 shape; 0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -264,6 +268,44 @@ def main():
         del Xd, Yd, vd, Pd, idd, d2d
         progress(f"autograd timing at n={nd} done")
 
+    # --- interpolated repulsion (tsne_kl_grad_fft) against the exact pass ---
+    interp = {}
+    if args.fft_n:
+        wf = synth.WORKLOADS["c5"]
+        nf = args.fft_n
+        Xf = torch.from_numpy(synth.make_points(wf, n=nf)[0]).to(dev)
+        wsf = api.Workspace()
+        idf, d2f = api.knn(Xf, wf.k, "bf16", n_cand=wf.candidates, ws=wsf)
+        Pf = api.symmetrize(idf, api.calibrate_P(d2f, wf.perplexity)[0], ws=wsf)
+        del Xf, idf, d2f
+        std = 30.0  # a spread embedding (late-iteration scale) of the c5 point count
+        Yf = torch.from_numpy(synth.random_embedding(nf, std, 4242)).to(dev)
+        wse, wsi = api.Workspace(), api.Workspace()
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                out = fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            return float(np.median(ts)), out
+
+        te, (ge, Ze, _, _) = timed(lambda: api.kl_grad(Yf, Pf, 1.0, want_Z=True, ws=wse), 3)
+        tf, (gf, Zf, _) = timed(lambda: api.kl_grad_fft(Yf, Pf, 1.0, want_Z=True, ws=wsi), 10)
+        interp = {"n": nf, "nnz": int(Pf.nnz), "embedding": f"N(0, {std:g}^2 I), float32, seed 4242",
+                  "n_interp": 3, "min_boxes": 50, "max_box_width": 1.0, "max_fft": 2048,
+                  "exact_ms": te, "interpolated_ms": tf, "speedup": te / tf,
+                  "grad_rel_err_vs_exact": float(torch.linalg.norm(gf - ge) / torch.linalg.norm(ge)),
+                  "Z_rel_err_vs_exact": abs(Zf.item() - Ze.item()) / Ze.item()}
+        del Yf, Pf, ge, gf, wse, wsi, wsf
+        progress(f"interpolated gradient at n={nf} done")
+
     # --- CPU baseline: the FP64 oracle on a bounded sample ------------------
     cpu = None
     errors = {}
@@ -366,6 +408,7 @@ def main():
         "iteration_pairs_per_s": float(n) * (n - 1) / (iter_ms * 1e-3),
         "knn_build_s": {f"{w.knn}_in_step": knn_fp32_s, **knn_cmp},
         "kl_autograd": diff,
+        "interpolated_gradient": interp,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "errors_vs_fp64": errors,
