@@ -14,6 +14,9 @@
  *            Tree-Based Algorithms", Sec. 4.1 (sparse P on the exact
  *            k = 3*perplexity nearest-neighbour graph).
  *   [Jac88]  Jacobs, Neural Networks 1 (1988): per-parameter gains.
+ *   [HMT11]  Halko, Martinsson & Tropp, SIAM Review 53 (2011), "Finding
+ *            structure with randomness": Algorithm 4.4 (randomized
+ *            subspace iteration), Algorithm 5.1 (direct SVD) -- tsne_pca.
  *   [LRHSK19] Linderman, Rachh, Hoskins, Steinerberger & Kluger, Nat.
  *            Methods 16 (2019), "Fast interpolation-based t-SNE for
  *            improved visualization of single-cell RNA-seq data":
@@ -215,6 +218,34 @@ int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_
 int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                      float exaggeration, int32_t n_interp, int32_t min_boxes, float max_box_width, int32_t max_fft,
                      float* grad, double* Z, double* kl, void* workspace, size_t* workspace_bytes, void* stream);
+
+/*
+ * tsne_pca -- principal components of X (the step that produces the PCA
+ * scores t-SNE embeds): randomized truncated SVD of the column-centred
+ * Xc = X - 1 mu^T [HMT11 Alg. 4.4 + 5.1] with a subspace of l = 64 columns:
+ *   Q = orth(Xc Omega); q times: Q = orth(Xc orth(Xc^T Q));
+ *   Z = Xc^T Q, Z^T Z = U diag(s^2) U^T (s descending);
+ *   components = (Z U diag(1/s))^T, scores = Q U diag(s) (= Xc components^T
+ *   when Q spans the range of Xc).
+ * orth() is the Q factor with a positive R diagonal (CholeskyQR2 here).
+ * Sign convention: each component's entry of largest magnitude is positive
+ * (the first on ties); the scores follow.  Products with X run on the FP32
+ * matrix cores, the 64 x 64 steps in FP64; bitwise reproducible.  Xc must
+ * have rank >= 64 (else the trailing directions are not defined).
+ *
+ *   X          [n][g] float, read-only; 64 <= n <= 65535 * 4096, 64 <= g <= 2^20.
+ *   k          components returned, 1..64.
+ *   q          power iterations, 0..16 (2).
+ *   omega      [g][64] float, read-only: the random test matrix (the caller
+ *              draws it, e.g. i.i.d. N(0, 1)).
+ *   scores     [n][k] float out.
+ *   components [k][g] float out (orthonormal rows).
+ *   singular_values [k] double out (device).
+ *   mean       [g] float out: the column means.
+ */
+int tsne_pca(const float* X, int64_t n, int32_t g, int32_t k, int32_t q, const float* omega, float* scores,
+             float* components, double* singular_values, float* mean, void* workspace, size_t* workspace_bytes,
+             void* stream);
 
 /*
  * tsne_step -- one optimiser step, gradient descent with momentum

@@ -48,6 +48,7 @@ SIGNATURES = {
     "tsne_kl_grad": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_kl_grad_fft": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _i32, _i32, _f32, _i32, _p, _p, _p, _p, _szp,
                                    _p]),
+    "tsne_pca": (C.c_int, [_p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_step": (C.c_int, [_p, _p, _p, _p, _i64, _f32, _f32, _f32, _f32, _f32, _p]),
     "tsne_optimize": (C.c_int, [_p, _p, _p, _i64, _p, _p, _p, _i64, _i32, _i32, C.POINTER(Schedule), _i32, _p, _p,
                                 _p, _szp, _p]),

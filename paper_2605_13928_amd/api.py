@@ -195,6 +195,27 @@ def kl_grad_fft(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, n_interp
     return grad, Z, kl
 
 
+PCA_SUBSPACE = 64
+
+
+def pca(X: torch.Tensor, k: int, omega: torch.Tensor, q: int = 2, ws: Workspace | None = None):
+    """Randomized PCA (tsne_pca).  X [n, g] f32, omega [g, 64] f32.
+    Returns (scores [n, k] f32, components [k, g] f32, singular values [k] f64, mean [g] f32)."""
+    _req(X, "X", torch.float32)
+    n, g = X.shape
+    _req(omega, "omega", torch.float32, (g, PCA_SUBSPACE))
+    dev = X.device
+    scores = torch.empty((n, k), dtype=torch.float32, device=dev)
+    comps = torch.empty((k, g), dtype=torch.float32, device=dev)
+    sv = torch.empty(k, dtype=torch.float64, device=dev)
+    mean = torch.empty(g, dtype=torch.float32, device=dev)
+    L = _lib.load()
+    _run_with_workspace("tsne_pca", L.tsne_pca,
+                        (_ptr(X), n, g, int(k), int(q), _ptr(omega), _ptr(scores), _ptr(comps), _ptr(sv), _ptr(mean)),
+                        (_stream(dev),), dev, ws, key=("pca", n, g))
+    return scores, comps, sv, mean
+
+
 def step(Y, update, gains, grad, lr: float, momentum: float, gain_inc: float = 0.2, gain_dec: float = 0.8,
          min_gain: float = 0.01):
     """In-place momentum + gains step on [n, 2] float32 tensors."""

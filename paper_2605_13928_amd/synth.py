@@ -26,6 +26,8 @@ __all__ = [
     "make_init",
     "random_embedding",
     "random_knn_graph",
+    "make_expression",
+    "make_omega",
     "sha256",
 ]
 
@@ -159,6 +161,28 @@ def random_knn_graph(n: int, k: int, seed: int, scale: float = 100.0):
     idx = (np.arange(n, dtype=np.int64)[:, None] + off) % n
     d2 = np.sort(rng.chisquare(50, size=(n, k)) * (scale / 50.0), axis=1)
     return np.ascontiguousarray(idx, dtype=np.int32), np.ascontiguousarray(d2, dtype=np.float32)
+
+
+def make_expression(n: int, g: int, seed: int, latent: int = 64, top: float = 100.0, bottom: float = 1.0,
+                    noise: float = 0.05, offset: float = 2.0) -> np.ndarray:
+    """Expression-like X [n, g] float32 (the input of the PCA step): cells with
+    `latent` hidden factors of geometrically decaying scale (top .. bottom),
+    mapped to g genes by an orthonormal loading matrix, plus i.i.d. N(0,
+    noise^2) and a constant offset; a smooth spectrum over a noise floor."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    scales = np.geomspace(top, bottom, latent)
+    Lat = (rng.standard_normal((n, latent)) * scales).astype(np.float32)
+    F = np.linalg.qr(rng.standard_normal((g, latent)))[0].T.astype(np.float32)  # latent x g, orthonormal rows
+    X = Lat @ F
+    X += offset
+    X += (rng.standard_normal((n, g)) * noise).astype(np.float32)
+    return np.ascontiguousarray(X, dtype=np.float32)
+
+
+def make_omega(g: int, seed: int, width: int = 64) -> np.ndarray:
+    """Gaussian test matrix Omega [g, width] float32 of the randomized PCA."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.ascontiguousarray(rng.standard_normal((g, width)), dtype=np.float32)
 
 
 def sha256(a: np.ndarray) -> str:

@@ -111,6 +111,17 @@ def test_invalid_arguments_rejected(L):
     assert fq(mf=32)[0] == IA and fq(mf=8192)[0] == IA and fq(mf=1000)[0] == IA
     assert fq(p=5, mb=50, mf=256)[0] == IA  # 2 p min_boxes > max_fft
     assert fq(p=2, mb=16, mf=64)[0] == 0
+    # randomized PCA: 64 <= n, 64 <= g, 1 <= k <= 64, 0 <= q <= 16
+    pc = L.tsne_pca
+
+    def pq(n=1000, g=300, k=50, q=2, om=fake):
+        return ws_query(pc, fake, n, g, k, q, om, fake, fake, fake, fake)
+
+    rc, need = pq()
+    assert rc == 0 and need >= 2 * 1000 * 64 * 4 + 300 * 64 * 4
+    assert pq(n=63)[0] == IA and pq(g=63)[0] == IA and pq(k=0)[0] == IA and pq(k=65)[0] == IA
+    assert pq(q=-1)[0] == IA and pq(q=17)[0] == IA and pq(om=NULL)[0] == IA
+    assert pq(n=65535 * 4096 + 1)[0] == UN
     st = L.tsne_step
     assert st(NULL, fake, fake, fake, 10, C.c_float(200), C.c_float(0.5), C.c_float(0.2), C.c_float(0.8),
               C.c_float(0.01), NULL) == IA
