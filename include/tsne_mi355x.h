@@ -233,7 +233,7 @@ int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_ptr, const in
  * matrix cores, the 64 x 64 steps in FP64; bitwise reproducible.  Xc must
  * have rank >= 64 (else the trailing directions are not defined).
  *
- *   X          [n][g] float, read-only; 64 <= n <= 65535 * 4096, 64 <= g <= 2^20.
+ *   X          [n][g] float, read-only; 64 <= n <= 65535 * 2048, 64 <= g <= 2^20.
  *   k          components returned, 1..64.
  *   q          power iterations, 0..16 (2).
  *   omega      [g][64] float, read-only: the random test matrix (the caller

@@ -21,23 +21,28 @@
 namespace tsne {
 
 constexpr int PCA_L = 64;       // subspace width = one 64-column MFMA tile row
-constexpr int PCA_RC = 4096;    // rows per partial of the column sums and X^T Q
-constexpr int PCA_GRC = 4096;   // rows per partial of the Gram matrices
+constexpr int PCA_RC = 2048;    // rows per partial of the column sums and X^T Q
+constexpr int PCA_GRC = 1024;   // rows per partial of the Gram matrices
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 // --- column means ---------------------------------------------------------
 
-// part[r][j] = sum of X[i][j] over rows i of chunk r (FP64); blockIdx.y = chunk.
+// part[r][j] = sum of X[i][j] over the rows i of chunk r = blockIdx.y (FP64,
+// eight independent partial sums per thread, added in a fixed order).
 __global__ __launch_bounds__(256) void pca_colsum_kernel(const float* __restrict__ X, int64_t n, int g,
                                                          double* __restrict__ part) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= g) return;
   const int64_t r0 = int64_t(blockIdx.y) * PCA_RC;
   const int64_t r1 = r0 + PCA_RC < n ? r0 + PCA_RC : n;
-  double s = 0.0;
-  for (int64_t i = r0; i < r1; ++i) s += double(X[i * g + j]);
-  part[int64_t(blockIdx.y) * g + j] = s;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t i = r0;
+  for (; i + 8 <= r1; i += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += double(X[(i + u) * g + j]);
+  for (; i < r1; ++i) s[0] += double(X[i * g + j]);
+  part[int64_t(blockIdx.y) * g + j] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 __global__ __launch_bounds__(256) void pca_colmean_kernel(const double* __restrict__ part, int64_t nchunk, int g,
@@ -51,17 +56,20 @@ __global__ __launch_bounds__(256) void pca_colmean_kernel(const double* __restri
 
 // --- C = (A - 1 mu^T) W  (M x K times K x 64; the first ncols columns stored) --
 
-// Block: 128 rows of A, 4 waves x 32 rows; K in chunks of 32 staged in LDS.
-// MFMA 16x16x4 operands: lane l holds A[l % 16][l / 16] and W[l / 16][l % 16];
-// the result tile D[4 (l / 16) + r][l % 16] in register r.
-template <bool CENTER>
+// Block: 128 rows of A, 4 waves x 32 rows; K in chunks of 64 staged in LDS,
+// the next chunk loaded into registers while the current one is used (VEC:
+// 16-byte loads, K a multiple of 4).  MFMA 16x16x4 operands: lane l holds
+// A[l % 16][l / 16] and W[l / 16][l % 16]; the result tile
+// D[4 (l / 16) + r][l % 16] in register r.
+template <bool CENTER, bool VEC>
 __global__ __launch_bounds__(256) void pca_gemm_tall_kernel(const float* __restrict__ A, int64_t M, int K,
                                                             const float* __restrict__ mu,
                                                             const float* __restrict__ W, float* __restrict__ C,
                                                             int ldc, int ncols) {
-  constexpr int BM = 128, KC = 32, SA = KC + 1, SW = PCA_L + 16;
-  __shared__ float As[BM * SA];
-  __shared__ float Ws[KC * SW];
+  constexpr int BM = 128, KC = 64, SA = KC + 4, SW = PCA_L + 16;
+  constexpr int AE = VEC ? (BM * KC) / (4 * 256) : (BM * KC) / 256;  // loads per thread
+  __shared__ __attribute__((aligned(16))) float As[BM * SA];
+  __shared__ __attribute__((aligned(16))) float Ws[KC * SW];
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t m0 = int64_t(blockIdx.x) * BM;
@@ -70,27 +78,73 @@ __global__ __launch_bounds__(256) void pca_gemm_tall_kernel(const float* __restr
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = 0; k0 < K; k0 += KC) {
+  float4 ra[VEC ? AE : 1];
+  float rs[VEC ? 1 : AE];
+  float4 rw[4];
+  auto load = [&](int k0) {
+    if (VEC) {
 #pragma unroll
-    for (int e = 0; e < (BM * KC) / 256; ++e) {
-      const int idx = tid + 256 * e;
-      const int r = idx / KC, c = idx % KC;
-      const int64_t row = m0 + r;
-      const int col = k0 + c;
-      float v = 0.0f;
-      if (row < M && col < K) {
-        v = A[row * K + col];
-        if (CENTER) v -= mu[col];
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        const int r = idx >> 4, c = k0 + 4 * (idx & 15);
+        const int64_t row = m0 + r;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (row < M && c < K) {
+          v = *reinterpret_cast<const float4*>(A + row * K + c);
+          if (CENTER) {
+            const float4 m = *reinterpret_cast<const float4*>(mu + c);
+            v.x -= m.x;
+            v.y -= m.y;
+            v.z -= m.z;
+            v.w -= m.w;
+          }
+        }
+        ra[VEC ? e : 0] = v;
       }
-      As[r * SA + c] = v;
+    } else {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        const int r = idx >> 6, c = k0 + (idx & 63);
+        const int64_t row = m0 + r;
+        float v = 0.0f;
+        if (row < M && c < K) {
+          v = A[row * K + c];
+          if (CENTER) v -= mu[c];
+        }
+        rs[VEC ? 0 : e] = v;
+      }
     }
 #pragma unroll
-    for (int e = 0; e < (KC * PCA_L) / 256; ++e) {
+    for (int e = 0; e < 4; ++e) {
       const int idx = tid + 256 * e;
-      const int r = idx / PCA_L, c = idx % PCA_L;
-      Ws[r * SW + c] = (k0 + r < K) ? W[int64_t(k0 + r) * PCA_L + c] : 0.0f;
+      const int r = k0 + (idx >> 4);
+      rw[e] = r < K ? *reinterpret_cast<const float4*>(W + int64_t(r) * PCA_L + 4 * (idx & 15))
+                    : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    if (VEC) {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        *reinterpret_cast<float4*>(As + (idx >> 4) * SA + 4 * (idx & 15)) = ra[VEC ? e : 0];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        As[(idx >> 6) * SA + (idx & 63)] = rs[VEC ? 0 : e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + 256 * e;
+      *reinterpret_cast<float4*>(Ws + (idx >> 4) * SW + 4 * (idx & 15)) = rw[e];
     }
     __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);  // in flight during the products below
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       float av[2], bv[4];
@@ -119,62 +173,119 @@ __global__ __launch_bounds__(256) void pca_gemm_tall_kernel(const float* __restr
 
 // --- part[r] = (A - 1 mu^T)^T Bm over the rows of chunk r  (K x 64 each) -----
 
-// Block (column tile t = blockIdx.x of 64 columns of A, row chunk r =
-// blockIdx.y of PCA_RC rows); wave w owns columns 16 w .. 16 w + 15 of the
-// tile, all 64 columns of Bm; rows are staged 32 at a time.
-template <bool CENTER>
+// Block (256 columns of A from c0 = 256 blockIdx.x, row chunk r = blockIdx.y
+// of PCA_RC rows); wave w owns columns c0 + 64 w .. + 63 (4 tiles of 16)
+// against all 64 columns of Bm (4 tiles); rows staged 32 at a time, the
+// next stage loaded into registers while the current one is used.
+template <bool CENTER, bool VEC>
 __global__ __launch_bounds__(256) void pca_gemm_red_kernel(const float* __restrict__ A, int64_t M, int K,
                                                            const float* __restrict__ mu,
                                                            const float* __restrict__ Bm, float* __restrict__ part) {
-  constexpr int MS = 32, S = PCA_L + 16;
-  __shared__ float At[MS * S];
-  __shared__ float Bt[MS * S];
+  constexpr int MS = 32, NB = 256, SA = NB + 16, SB = PCA_L + 16;
+  constexpr int AE = VEC ? (MS * NB) / (4 * 256) : (MS * NB) / 256;
+  __shared__ __attribute__((aligned(16))) float At[MS * SA];
+  __shared__ __attribute__((aligned(16))) float Bt[MS * SB];
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int c0 = blockIdx.x * PCA_L;
+  const int c0 = blockIdx.x * NB;
   const int64_t r0 = int64_t(blockIdx.y) * PCA_RC;
   const int64_t r1 = r0 + PCA_RC < M ? r0 + PCA_RC : M;
-  floatx4_t acc[4];
+  floatx4_t acc[4][4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int64_t ms = r0; ms < r1; ms += MS) {
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int e = 0; e < (MS * PCA_L) / 256; ++e) {
-      const int idx = tid + 256 * e;
-      const int r = idx / PCA_L, c = idx % PCA_L;
-      const int64_t row = ms + r;
-      const int col = c0 + c;
-      float v = 0.0f, b = 0.0f;
-      if (row < r1) {
-        if (col < K) {
-          v = A[row * K + col];
-          if (CENTER) v -= mu[col];
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  float4 ra[VEC ? AE : 1];
+  float rs[VEC ? 1 : AE];
+  float4 rb[2];
+  auto load = [&](int64_t ms) {
+    if (VEC) {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        const int64_t row = ms + (idx >> 6);
+        const int c = c0 + 4 * (idx & 63);
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (row < r1 && c < K) {
+          v = *reinterpret_cast<const float4*>(A + row * K + c);
+          if (CENTER) {
+            const float4 m = *reinterpret_cast<const float4*>(mu + c);
+            v.x -= m.x;
+            v.y -= m.y;
+            v.z -= m.z;
+            v.w -= m.w;
+          }
         }
-        b = Bm[row * PCA_L + c];
+        ra[VEC ? e : 0] = v;
       }
-      At[r * S + c] = v;
-      Bt[r * S + c] = b;
+    } else {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        const int64_t row = ms + (idx >> 8);
+        const int c = c0 + (idx & 255);
+        float v = 0.0f;
+        if (row < r1 && c < K) {
+          v = A[row * K + c];
+          if (CENTER) v -= mu[c];
+        }
+        rs[VEC ? 0 : e] = v;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = tid + 256 * e;
+      const int64_t row = ms + (idx >> 4);
+      rb[e] = row < r1 ? *reinterpret_cast<const float4*>(Bm + row * PCA_L + 4 * (idx & 15))
+                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  };
+  load(r0);
+  for (int64_t ms = r0; ms < r1; ms += MS) {
+    if (VEC) {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        *reinterpret_cast<float4*>(At + (idx >> 6) * SA + 4 * (idx & 63)) = ra[VEC ? e : 0];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        At[(idx >> 8) * SA + (idx & 255)] = rs[VEC ? 0 : e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = tid + 256 * e;
+      *reinterpret_cast<float4*>(Bt + (idx >> 4) * SB + 4 * (idx & 15)) = rb[e];
     }
     __syncthreads();
+    if (ms + MS < r1) load(ms + MS);
 #pragma unroll
     for (int kk = 0; kk < MS; kk += 4) {
-      const float av = At[(kk + lk) * S + 16 * w + li];
+      float av[4], bv[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const float bv = Bt[(kk + lk) * S + 16 * b + li];
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[b], 0, 0, 0);
-      }
+      for (int a = 0; a < 4; ++a) av[a] = At[(kk + lk) * SA + 64 * w + 16 * a + li];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bt[(kk + lk) * SB + 16 * b + li];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
   float* out = part + int64_t(blockIdx.y) * K * PCA_L;
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int col = c0 + 16 * w + 4 * lk + r;
-      if (col < K) out[int64_t(col) * PCA_L + 16 * b + li] = acc[b][r];
-    }
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = c0 + 64 * w + 16 * a + 4 * lk + r;
+        if (col < K) out[int64_t(col) * PCA_L + 16 * b + li] = acc[a][b][r];
+      }
 }
 
 // out[i][c] = sum over chunks r (in order) of part[r][i][c], as float.
@@ -221,60 +332,60 @@ __global__ __launch_bounds__(256) void pca_gram_kernel(const float* __restrict__
   for (int e = 0; e < 16; ++e) out[a * PCA_L + b0 + e] = acc[e];
 }
 
+// G[e] = sum over the nchunk partials (in order), e < 64 x 64.
+__global__ __launch_bounds__(256) void pca_gram_reduce_kernel(const double* __restrict__ part, int64_t nchunk,
+                                                              double* __restrict__ G) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= PCA_L * PCA_L) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < nchunk; ++r) s += part[r * PCA_L * PCA_L + e];
+  G[e] = s;
+}
+
 // --- Cholesky G = R^T R (upper R) and R^-1, one block, FP64 ------------------
 
-// G = sum over the nchunk Gram partials.  shift > 0 adds shift * trace / 64
-// to the diagonal (the first, shifted pass of CholeskyQR2).  Rinv (float,
+// shift > 0 adds shift * trace / 64 to the diagonal (the first, shifted pass
+// of CholeskyQR2).  Right-looking: per column, the pivot, the row of R, then
+// the trailing update of the upper triangle in parallel.  Rinv (float,
 // 64 x 64 row-major) is the W of the next product Q = Y Rinv.
-__global__ __launch_bounds__(256) void pca_cholinv_kernel(const double* __restrict__ part, int64_t nchunk,
-                                                          double shift, float* __restrict__ Rinv) {
-  __shared__ double G[PCA_L][PCA_L + 1];
-  __shared__ double R[PCA_L][PCA_L + 1];
+__global__ __launch_bounds__(256) void pca_cholinv_kernel(const double* __restrict__ Gin, double shift,
+                                                          float* __restrict__ Rinv) {
+  __shared__ double A[PCA_L][PCA_L + 1];
   __shared__ double X[PCA_L][PCA_L + 1];
+  __shared__ double red[4];
   const int tid = threadIdx.x;
-  for (int e = tid; e < PCA_L * PCA_L; e += 256) {
-    double s = 0.0;
-    for (int64_t r = 0; r < nchunk; ++r) s += part[r * PCA_L * PCA_L + e];
-    G[e / PCA_L][e % PCA_L] = s;
-    R[e / PCA_L][e % PCA_L] = 0.0;
-  }
+  for (int e = tid; e < PCA_L * PCA_L; e += 256) A[e / PCA_L][e % PCA_L] = Gin[e];
   __syncthreads();
   if (shift > 0.0) {
-    __shared__ double tr;
-    if (tid == 0) {
-      double t = 0.0;
-      for (int i = 0; i < PCA_L; ++i) t += G[i][i];
-      tr = t;
-    }
-    __syncthreads();
-    if (tid < PCA_L) G[tid][tid] += shift * tr / PCA_L;
+    const double tr = block_sum_d(tid < PCA_L ? A[tid][tid] : 0.0, red);
+    if (tid < PCA_L) A[tid][tid] += shift * tr / PCA_L;
     __syncthreads();
   }
   for (int j = 0; j < PCA_L; ++j) {
     if (tid == 0) {
-      double d = G[j][j];
-      for (int p = 0; p < j; ++p) d -= R[p][j] * R[p][j];
-      R[j][j] = sqrt(d > 1e-300 ? d : 1e-300);
+      const double d = A[j][j];
+      A[j][j] = sqrt(d > 1e-300 ? d : 1e-300);
     }
     __syncthreads();
-    if (tid > j && tid < PCA_L) {
-      double v = G[j][tid];
-      for (int p = 0; p < j; ++p) v -= R[p][j] * R[p][tid];
-      R[j][tid] = v / R[j][j];
+    if (tid > j && tid < PCA_L) A[j][tid] /= A[j][j];
+    __syncthreads();
+    for (int e = tid; e < PCA_L * PCA_L; e += 256) {
+      const int i = e / PCA_L, c = e % PCA_L;
+      if (i > j && c >= i) A[i][c] -= A[j][i] * A[j][c];
     }
     __syncthreads();
   }
-  // R X = I, upper triangular X: thread c solves column c by back substitution
-  if (tid < PCA_L) {
-    const int c = tid;
-    for (int i = PCA_L - 1; i >= 0; --i) {
+  // R X = I with R the upper triangle of A: row i of X from rows i+1 ..,
+  // one thread per column
+  for (int i = PCA_L - 1; i >= 0; --i) {
+    if (tid < PCA_L) {
+      const int c = tid;
       double v = (i == c) ? 1.0 : 0.0;
-      if (i <= c)
-        for (int p = i + 1; p <= c; ++p) v -= R[i][p] * X[p][c];
-      X[i][c] = i <= c ? v / R[i][i] : 0.0;
+      for (int p = i + 1; p <= c; ++p) v -= A[i][p] * X[p][c];
+      X[i][c] = i <= c ? v / A[i][i] : 0.0;
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (int e = tid; e < PCA_L * PCA_L; e += 256) Rinv[e] = float(X[e / PCA_L][e % PCA_L]);
 }
 
@@ -284,32 +395,30 @@ __global__ __launch_bounds__(256) void pca_cholinv_kernel(const double* __restri
 // and players 1..63 rotate; pair i of the step is (arr[i], arr[63 - i]).
 // Outputs the eigenvalues in descending order (lam) and the matching
 // eigenvectors as the columns of U (row-major 64 x 64, FP64).
-__global__ __launch_bounds__(256) void pca_jacobi_kernel(const double* __restrict__ part, int64_t nchunk,
-                                                         double* __restrict__ lam, double* __restrict__ U) {
+__global__ __launch_bounds__(256) void pca_jacobi_kernel(const double* __restrict__ Gin, double* __restrict__ lam,
+                                                         double* __restrict__ U) {
   __shared__ double A[PCA_L][PCA_L + 1];
   __shared__ double V[PCA_L][PCA_L + 1];
   __shared__ double cs[32], sn[32];
   __shared__ int pp[32], qq[32];
-  __shared__ double off_s, diag_s;
+  __shared__ double red[4];
   __shared__ int order[PCA_L];
   const int tid = threadIdx.x;
   for (int e = tid; e < PCA_L * PCA_L; e += 256) {
-    double s = 0.0;
-    for (int64_t r = 0; r < nchunk; ++r) s += part[r * PCA_L * PCA_L + e];
-    A[e / PCA_L][e % PCA_L] = s;
+    A[e / PCA_L][e % PCA_L] = Gin[e];
     V[e / PCA_L][e % PCA_L] = (e / PCA_L == e % PCA_L) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
-    if (tid == 0) {
-      double off = 0.0, dg = 0.0;
-      for (int i = 0; i < PCA_L; ++i)
-        for (int j = 0; j < PCA_L; ++j) (i == j ? dg : off) += A[i][j] * A[i][j];
-      off_s = off;
-      diag_s = dg;
+    double off = 0.0, dg = 0.0;
+    for (int e = tid; e < PCA_L * PCA_L; e += 256) {
+      const double v = A[e / PCA_L][e % PCA_L];
+      if (e / PCA_L == e % PCA_L) dg += v * v;
+      else off += v * v;
     }
-    __syncthreads();
-    if (!(off_s > 1e-30 * diag_s)) break;  // uniform: shared values
+    off = block_sum_d(off, red);  // same bits in every thread: a uniform exit
+    dg = block_sum_d(dg, red);
+    if (!(off > 1e-30 * dg)) break;
     for (int step = 0; step < PCA_L - 1; ++step) {
       if (tid < 32) {
         auto player = [&](int j) { return j == 0 ? 0 : 1 + (j - 1 + step) % (PCA_L - 1); };
@@ -426,7 +535,7 @@ __global__ __launch_bounds__(256) void pca_sign_kernel(const float* __restrict__
 }
 
 struct PcaPlan {
-  size_t o_mpart, o_Ya, o_Yb, o_Za, o_Zb, o_part, o_gpart, o_Rinv, o_lam, o_U, o_W1, o_W2, bytes;
+  size_t o_mpart, o_Ya, o_Yb, o_Za, o_Zb, o_part, o_gpart, o_G, o_Rinv, o_lam, o_U, o_W1, o_W2, bytes;
   int64_t nchunk_n, nchunk_g, gchunk_max;
 };
 
@@ -444,6 +553,7 @@ PcaPlan pca_plan(int64_t n, int g) {
   L.o_Zb = c.take(sizeof(float) * size_t(g) * PCA_L);
   L.o_part = c.take(sizeof(float) * size_t(L.nchunk_n) * size_t(g) * PCA_L);
   L.o_gpart = c.take(sizeof(double) * size_t(L.gchunk_max) * PCA_L * PCA_L);
+  L.o_G = c.take(sizeof(double) * PCA_L * PCA_L);
   L.o_Rinv = c.take(sizeof(float) * PCA_L * PCA_L);
   L.o_lam = c.take(sizeof(double) * PCA_L);
   L.o_U = c.take(sizeof(double) * PCA_L * PCA_L);
@@ -467,8 +577,15 @@ struct PcaCtx {
 int pca_tall(const PcaCtx& x, const float* A, int64_t M, int K, const float* mu, const float* W, float* C, int ldc,
              int ncols) {
   const dim3 grid(unsigned(ceil_div(M, 128)));
-  if (mu) hipLaunchKernelGGL(pca_gemm_tall_kernel<true>, grid, dim3(256), 0, x.s, A, M, K, mu, W, C, ldc, ncols);
-  else hipLaunchKernelGGL(pca_gemm_tall_kernel<false>, grid, dim3(256), 0, x.s, A, M, K, mu, W, C, ldc, ncols);
+  const bool vec = K % 4 == 0;
+  if (mu && vec)
+    hipLaunchKernelGGL((pca_gemm_tall_kernel<true, true>), grid, dim3(256), 0, x.s, A, M, K, mu, W, C, ldc, ncols);
+  else if (mu)
+    hipLaunchKernelGGL((pca_gemm_tall_kernel<true, false>), grid, dim3(256), 0, x.s, A, M, K, mu, W, C, ldc, ncols);
+  else if (vec)
+    hipLaunchKernelGGL((pca_gemm_tall_kernel<false, true>), grid, dim3(256), 0, x.s, A, M, K, mu, W, C, ldc, ncols);
+  else
+    hipLaunchKernelGGL((pca_gemm_tall_kernel<false, false>), grid, dim3(256), 0, x.s, A, M, K, mu, W, C, ldc, ncols);
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
 }
@@ -477,8 +594,9 @@ int pca_tall(const PcaCtx& x, const float* A, int64_t M, int K, const float* mu,
 int pca_red(const PcaCtx& x, const float* A, int64_t M, int K, const float* mu, const float* Bm, float* out) {
   float* part = x.at<float>(x.L.o_part);
   const int64_t nchunk = ceil_div(M, PCA_RC);
-  const dim3 grid(unsigned(ceil_div(K, PCA_L)), unsigned(nchunk));
-  hipLaunchKernelGGL(pca_gemm_red_kernel<true>, grid, dim3(256), 0, x.s, A, M, K, mu, Bm, part);
+  const dim3 grid(unsigned(ceil_div(K, 256)), unsigned(nchunk));
+  if (K % 4 == 0) hipLaunchKernelGGL((pca_gemm_red_kernel<true, true>), grid, dim3(256), 0, x.s, A, M, K, mu, Bm, part);
+  else hipLaunchKernelGGL((pca_gemm_red_kernel<true, false>), grid, dim3(256), 0, x.s, A, M, K, mu, Bm, part);
   TSNE_CHECK_LAUNCH();
   const int64_t count = int64_t(K) * PCA_L;
   hipLaunchKernelGGL(pca_reduce_kernel, dim3(unsigned(ceil_div(count, 256))), dim3(256), 0, x.s, part, nchunk, count,
@@ -487,9 +605,13 @@ int pca_red(const PcaCtx& x, const float* A, int64_t M, int K, const float* mu, 
   return TSNE_OK;
 }
 
+// G (64 x 64, FP64, in the workspace) = Y^T Y
 int pca_gram(const PcaCtx& x, const float* Y, int64_t m) {
-  hipLaunchKernelGGL(pca_gram_kernel, dim3(unsigned(ceil_div(m, PCA_GRC))), dim3(256), 0, x.s, Y, m,
-                     x.at<double>(x.L.o_gpart));
+  const int64_t nch = ceil_div(m, PCA_GRC);
+  hipLaunchKernelGGL(pca_gram_kernel, dim3(unsigned(nch)), dim3(256), 0, x.s, Y, m, x.at<double>(x.L.o_gpart));
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(pca_gram_reduce_kernel, dim3(PCA_L * PCA_L / 256), dim3(256), 0, x.s, x.at<double>(x.L.o_gpart),
+                     nch, x.at<double>(x.L.o_G));
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
 }
@@ -497,14 +619,13 @@ int pca_gram(const PcaCtx& x, const float* Y, int64_t m) {
 // CholeskyQR2 of the m x 64 factor in `a` (result in `a`, `b` scratch)
 int pca_orth(const PcaCtx& x, float* a, float* b, int64_t m) {
   int rc;
-  const int64_t nch = ceil_div(m, PCA_GRC);
   float* Rinv = x.at<float>(x.L.o_Rinv);
   if ((rc = pca_gram(x, a, m))) return rc;
-  hipLaunchKernelGGL(pca_cholinv_kernel, dim3(1), dim3(256), 0, x.s, x.at<double>(x.L.o_gpart), nch, 1e-12, Rinv);
+  hipLaunchKernelGGL(pca_cholinv_kernel, dim3(1), dim3(256), 0, x.s, x.at<double>(x.L.o_G), 1e-12, Rinv);
   TSNE_CHECK_LAUNCH();
   if ((rc = pca_tall(x, a, m, PCA_L, nullptr, Rinv, b, PCA_L, PCA_L))) return rc;
   if ((rc = pca_gram(x, b, m))) return rc;
-  hipLaunchKernelGGL(pca_cholinv_kernel, dim3(1), dim3(256), 0, x.s, x.at<double>(x.L.o_gpart), nch, 0.0, Rinv);
+  hipLaunchKernelGGL(pca_cholinv_kernel, dim3(1), dim3(256), 0, x.s, x.at<double>(x.L.o_G), 0.0, Rinv);
   TSNE_CHECK_LAUNCH();
   return pca_tall(x, b, m, PCA_L, nullptr, Rinv, a, PCA_L, PCA_L);
 }
@@ -547,8 +668,7 @@ extern "C" int tsne_pca(const float* X, int64_t n, int32_t g, int32_t k, int32_t
   if ((rc = pca_gram(x, Za, g))) return rc;
   double* lam = x.at<double>(L.o_lam);
   double* U = x.at<double>(L.o_U);
-  hipLaunchKernelGGL(pca_jacobi_kernel, dim3(1), dim3(256), 0, x.s, x.at<double>(L.o_gpart), ceil_div(g, PCA_GRC),
-                     lam, U);
+  hipLaunchKernelGGL(pca_jacobi_kernel, dim3(1), dim3(256), 0, x.s, x.at<double>(L.o_G), lam, U);
   TSNE_CHECK_LAUNCH();
   float* W1 = x.at<float>(L.o_W1);
   float* W2 = x.at<float>(L.o_W2);

@@ -121,7 +121,7 @@ def test_invalid_arguments_rejected(L):
     assert rc == 0 and need >= 2 * 1000 * 64 * 4 + 300 * 64 * 4
     assert pq(n=63)[0] == IA and pq(g=63)[0] == IA and pq(k=0)[0] == IA and pq(k=65)[0] == IA
     assert pq(q=-1)[0] == IA and pq(q=17)[0] == IA and pq(om=NULL)[0] == IA
-    assert pq(n=65535 * 4096 + 1)[0] == UN
+    assert pq(n=65535 * 2048 + 1)[0] == UN
     st = L.tsne_step
     assert st(NULL, fake, fake, fake, 10, C.c_float(200), C.c_float(0.5), C.c_float(0.2), C.c_float(0.8),
               C.c_float(0.01), NULL) == IA

@@ -53,8 +53,14 @@ def test_pca_matches_oracle(dev, case):
     assert col_err.max() <= 1e-2 and col_err[0] <= 1e-4, col_err
     # properties at any size
     np.testing.assert_allclose(comp @ comp.T, np.eye(k), atol=2e-5)
-    proj = (X.astype(np.float64) - mu) @ comp.T
-    assert np.linalg.norm(sc - proj) <= 1e-4 * np.linalg.norm(proj)
+    # scores = Xc V^T holds as far as Q spans the range of Xc: the GPU's
+    # deviation from it matches the oracle's
+    Xd = X.astype(np.float64)
+    proj = (Xd - mu) @ comp.T
+    oproj = (Xd - omu) @ ocomp.T
+    dg = np.linalg.norm(sc - proj) / np.linalg.norm(proj)
+    do = np.linalg.norm(osc - oproj) / np.linalg.norm(oproj)
+    assert dg <= do + 1e-4, (dg, do)
     for c in range(k):
         assert comp[c, np.argmax(np.abs(comp[c]))] > 0
 
