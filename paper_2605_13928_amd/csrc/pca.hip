@@ -22,7 +22,8 @@ namespace tsne {
 
 constexpr int PCA_L = 64;       // subspace width = one 64-column MFMA tile row
 constexpr int PCA_RC = 2048;    // rows per partial of the column sums and X^T Q
-constexpr int PCA_GRC = 1024;   // rows per partial of the Gram matrices
+constexpr int PCA_GRC = 512;    // rows per partial of a Gram matrix (the least, where m allows)
+constexpr int PCA_GMAX = 1024;  // partials of a Gram matrix (at most)
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
@@ -58,7 +59,10 @@ __global__ __launch_bounds__(256) void pca_colmean_kernel(const double* __restri
 
 // Block: 128 rows of A, 4 waves x 32 rows; K in chunks of 64 staged in LDS,
 // the next chunk loaded into registers while the current one is used (VEC:
-// 16-byte loads, K a multiple of 4).  MFMA 16x16x4 operands: lane l holds
+// 16-byte loads, K a multiple of 4).  The loads are unconditional, their
+// addresses clamped into the matrices, so that none waits inside a branch:
+// rows past M and columns past K are zeroed, and the mean subtracted, when
+// the registers are written to LDS.  MFMA 16x16x4 operands: lane l holds
 // A[l % 16][l / 16] and W[l / 16][l % 16]; the result tile
 // D[4 (l / 16) + r][l % 16] in register r.
 template <bool CENTER, bool VEC>
@@ -68,11 +72,15 @@ __global__ __launch_bounds__(256) void pca_gemm_tall_kernel(const float* __restr
                                                             int ldc, int ncols) {
   constexpr int BM = 128, KC = 64, SA = KC + 4, SW = PCA_L + 16;
   constexpr int AE = VEC ? (BM * KC) / (4 * 256) : (BM * KC) / 256;  // loads per thread
+  constexpr int RSTEP = VEC ? 16 : 4;                                // rows between a thread's loads
   __shared__ __attribute__((aligned(16))) float As[BM * SA];
   __shared__ __attribute__((aligned(16))) float Ws[KC * SW];
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t m0 = int64_t(blockIdx.x) * BM;
+  // this thread's A column offset within a chunk and first row within the block
+  const int ac = VEC ? 4 * (tid & 15) : (tid & 63);
+  const int ar = VEC ? (tid >> 4) : (tid >> 6);
   floatx4_t acc[2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -80,68 +88,53 @@ __global__ __launch_bounds__(256) void pca_gemm_tall_kernel(const float* __restr
     for (int b = 0; b < 4; ++b) acc[a][b] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
   float4 ra[VEC ? AE : 1];
   float rs[VEC ? 1 : AE];
+  float4 rm = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   float4 rw[4];
   auto load = [&](int k0) {
-    if (VEC) {
+    const int c = k0 + ac < K ? k0 + ac : 0;
 #pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int idx = tid + 256 * e;
-        const int r = idx >> 4, c = k0 + 4 * (idx & 15);
-        const int64_t row = m0 + r;
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (row < M && c < K) {
-          v = *reinterpret_cast<const float4*>(A + row * K + c);
-          if (CENTER) {
-            const float4 m = *reinterpret_cast<const float4*>(mu + c);
-            v.x -= m.x;
-            v.y -= m.y;
-            v.z -= m.z;
-            v.w -= m.w;
-          }
-        }
-        ra[VEC ? e : 0] = v;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int idx = tid + 256 * e;
-        const int r = idx >> 6, c = k0 + (idx & 63);
-        const int64_t row = m0 + r;
-        float v = 0.0f;
-        if (row < M && c < K) {
-          v = A[row * K + c];
-          if (CENTER) v -= mu[c];
-        }
-        rs[VEC ? 0 : e] = v;
-      }
+    for (int e = 0; e < AE; ++e) {
+      const int64_t row = m0 + ar + RSTEP * e;
+      const float* src = A + (row < M ? row : M - 1) * K + c;
+      if (VEC) ra[VEC ? e : 0] = *reinterpret_cast<const float4*>(src);
+      else rs[VEC ? 0 : e] = *src;
+    }
+    if (CENTER) {
+      if (VEC) rm = *reinterpret_cast<const float4*>(mu + c);
+      else rm.x = mu[c];
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int idx = tid + 256 * e;
-      const int r = k0 + (idx >> 4);
-      rw[e] = r < K ? *reinterpret_cast<const float4*>(W + int64_t(r) * PCA_L + 4 * (idx & 15))
-                    : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      const int r = k0 + (tid >> 4) + 16 * e;
+      rw[e] = *reinterpret_cast<const float4*>(W + int64_t(r < K ? r : K - 1) * PCA_L + 4 * (tid & 15));
     }
   };
   load(0);
   for (int k0 = 0; k0 < K; k0 += KC) {
-    if (VEC) {
+    const bool cok = k0 + ac < K;
 #pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int idx = tid + 256 * e;
-        *reinterpret_cast<float4*>(As + (idx >> 4) * SA + 4 * (idx & 15)) = ra[VEC ? e : 0];
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int idx = tid + 256 * e;
-        As[(idx >> 6) * SA + (idx & 63)] = rs[VEC ? 0 : e];
+    for (int e = 0; e < AE; ++e) {
+      const bool ok = cok && m0 + ar + RSTEP * e < M;
+      float* dst = As + (ar + RSTEP * e) * SA + ac;
+      if (VEC) {
+        float4 v = ra[VEC ? e : 0];
+        if (CENTER) {
+          v.x -= rm.x;
+          v.y -= rm.y;
+          v.z -= rm.z;
+          v.w -= rm.w;
+        }
+        *reinterpret_cast<float4*>(dst) = ok ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      } else {
+        const float v = CENTER ? rs[VEC ? 0 : e] - rm.x : rs[VEC ? 0 : e];
+        *dst = ok ? v : 0.0f;
       }
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int idx = tid + 256 * e;
-      *reinterpret_cast<float4*>(Ws + (idx >> 4) * SW + 4 * (idx & 15)) = rw[e];
+      const int r = (tid >> 4) + 16 * e;
+      *reinterpret_cast<float4*>(Ws + r * SW + 4 * (tid & 15)) =
+          k0 + r < K ? rw[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     __syncthreads();
     if (k0 + KC < K) load(k0 + KC);  // in flight during the products below
@@ -176,13 +169,16 @@ __global__ __launch_bounds__(256) void pca_gemm_tall_kernel(const float* __restr
 // Block (256 columns of A from c0 = 256 blockIdx.x, row chunk r = blockIdx.y
 // of PCA_RC rows); wave w owns columns c0 + 64 w .. + 63 (4 tiles of 16)
 // against all 64 columns of Bm (4 tiles); rows staged 32 at a time, the
-// next stage loaded into registers while the current one is used.
+// next stage loaded into registers while the current one is used.  As in
+// the tall product, the loads are unconditional (clamped addresses) and the
+// zeroing and centring happen on the way to LDS.
 template <bool CENTER, bool VEC>
 __global__ __launch_bounds__(256) void pca_gemm_red_kernel(const float* __restrict__ A, int64_t M, int K,
                                                            const float* __restrict__ mu,
                                                            const float* __restrict__ Bm, float* __restrict__ part) {
   constexpr int MS = 32, NB = 256, SA = NB + 16, SB = PCA_L + 16;
   constexpr int AE = VEC ? (MS * NB) / (4 * 256) : (MS * NB) / 256;
+  constexpr int RSTEP = VEC ? 4 : 1;  // rows between a thread's loads
   __shared__ __attribute__((aligned(16))) float At[MS * SA];
   __shared__ __attribute__((aligned(16))) float Bt[MS * SB];
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
@@ -190,6 +186,16 @@ __global__ __launch_bounds__(256) void pca_gemm_red_kernel(const float* __restri
   const int c0 = blockIdx.x * NB;
   const int64_t r0 = int64_t(blockIdx.y) * PCA_RC;
   const int64_t r1 = r0 + PCA_RC < M ? r0 + PCA_RC : M;
+  // this thread's column of A (fixed for the block) and first row of a stage
+  const int ac = VEC ? 4 * (tid & 63) : tid;
+  const int ar = VEC ? (tid >> 6) : 0;
+  const bool cok = c0 + ac < K;
+  const int c = cok ? c0 + ac : 0;
+  float4 rm = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (CENTER) {
+    if (VEC) rm = *reinterpret_cast<const float4*>(mu + c);
+    else rm.x = mu[c];
+  }
   floatx4_t acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -199,66 +205,44 @@ __global__ __launch_bounds__(256) void pca_gemm_red_kernel(const float* __restri
   float rs[VEC ? 1 : AE];
   float4 rb[2];
   auto load = [&](int64_t ms) {
-    if (VEC) {
 #pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int idx = tid + 256 * e;
-        const int64_t row = ms + (idx >> 6);
-        const int c = c0 + 4 * (idx & 63);
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (row < r1 && c < K) {
-          v = *reinterpret_cast<const float4*>(A + row * K + c);
-          if (CENTER) {
-            const float4 m = *reinterpret_cast<const float4*>(mu + c);
-            v.x -= m.x;
-            v.y -= m.y;
-            v.z -= m.z;
-            v.w -= m.w;
-          }
-        }
-        ra[VEC ? e : 0] = v;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int idx = tid + 256 * e;
-        const int64_t row = ms + (idx >> 8);
-        const int c = c0 + (idx & 255);
-        float v = 0.0f;
-        if (row < r1 && c < K) {
-          v = A[row * K + c];
-          if (CENTER) v -= mu[c];
-        }
-        rs[VEC ? 0 : e] = v;
-      }
+    for (int e = 0; e < AE; ++e) {
+      const int64_t row = ms + ar + RSTEP * e;
+      const float* src = A + (row < r1 ? row : r1 - 1) * K + c;
+      if (VEC) ra[VEC ? e : 0] = *reinterpret_cast<const float4*>(src);
+      else rs[VEC ? 0 : e] = *src;
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const int idx = tid + 256 * e;
-      const int64_t row = ms + (idx >> 4);
-      rb[e] = row < r1 ? *reinterpret_cast<const float4*>(Bm + row * PCA_L + 4 * (idx & 15))
-                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      const int64_t row = ms + (tid >> 4) + 16 * e;
+      rb[e] = *reinterpret_cast<const float4*>(Bm + (row < r1 ? row : r1 - 1) * PCA_L + 4 * (tid & 15));
     }
   };
   load(r0);
   for (int64_t ms = r0; ms < r1; ms += MS) {
-    if (VEC) {
 #pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int idx = tid + 256 * e;
-        *reinterpret_cast<float4*>(At + (idx >> 6) * SA + 4 * (idx & 63)) = ra[VEC ? e : 0];
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int idx = tid + 256 * e;
-        At[(idx >> 8) * SA + (idx & 255)] = rs[VEC ? 0 : e];
+    for (int e = 0; e < AE; ++e) {
+      const bool ok = cok && ms + ar + RSTEP * e < r1;
+      float* dst = At + (ar + RSTEP * e) * SA + ac;
+      if (VEC) {
+        float4 v = ra[VEC ? e : 0];
+        if (CENTER) {
+          v.x -= rm.x;
+          v.y -= rm.y;
+          v.z -= rm.z;
+          v.w -= rm.w;
+        }
+        *reinterpret_cast<float4*>(dst) = ok ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      } else {
+        const float v = CENTER ? rs[VEC ? 0 : e] - rm.x : rs[VEC ? 0 : e];
+        *dst = ok ? v : 0.0f;
       }
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const int idx = tid + 256 * e;
-      *reinterpret_cast<float4*>(Bt + (idx >> 4) * SB + 4 * (idx & 15)) = rb[e];
+      const int r = (tid >> 4) + 16 * e;
+      *reinterpret_cast<float4*>(Bt + r * SB + 4 * (tid & 15)) =
+          ms + r < r1 ? rb[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     __syncthreads();
     if (ms + MS < r1) load(ms + MS);
@@ -300,61 +284,116 @@ __global__ __launch_bounds__(256) void pca_reduce_kernel(const float* __restrict
 
 // --- Gram matrix Y^T Y of an m x 64 factor, FP64 -------------------------
 
-// Block r sums rows [r PCA_GRC, ...): thread t owns entries (t / 4, 16 (t % 4) + e).
-__global__ __launch_bounds__(256) void pca_gram_kernel(const float* __restrict__ Y, int64_t m,
+// Block r sums rows [r rpb, (r + 1) rpb) of Y (rpb a multiple of 32).  Rows
+// are staged 32 at a time in LDS as doubles, the next stage loaded into
+// registers (clamped addresses, rows past the end zeroed on the way to LDS)
+// while the current one is used; wave w takes rows w, w + 4, ... of a stage
+// and lane l accumulates the 8 x 8 entries (8 (l / 8) + i, 8 (l % 8) + j).
+// The four waves' sums are added in wave order.
+__global__ __launch_bounds__(256) void pca_gram_kernel(const float* __restrict__ Y, int64_t m, int64_t rpb,
                                                        double* __restrict__ part) {
   constexpr int RS = 32;
-  __shared__ float ys[RS * PCA_L];
-  const int tid = threadIdx.x;
-  const int a = tid >> 2, b0 = 16 * (tid & 3);
-  const int64_t r0 = int64_t(blockIdx.x) * PCA_GRC;
-  const int64_t r1 = r0 + PCA_GRC < m ? r0 + PCA_GRC : m;
-  double acc[16];
+  __shared__ __attribute__((aligned(16))) double ys[RS * PCA_L];
+  __shared__ double sum[PCA_L * PCA_L];
+  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int ia = 8 * (lane >> 3), ib = 8 * (lane & 7);
+  const int64_t r0 = int64_t(blockIdx.x) * rpb;
+  const int64_t r1 = r0 + rpb < m ? r0 + rpb : m;
+  double acc[8][8];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+  float4 rv[2];
+  auto load = [&](int64_t s) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int64_t row = s + (tid >> 4) + 16 * e;
+      rv[e] = *reinterpret_cast<const float4*>(Y + (row < r1 ? row : r1 - 1) * PCA_L + 4 * (tid & 15));
+    }
+  };
+  load(r0);
   for (int64_t s = r0; s < r1; s += RS) {
 #pragma unroll
-    for (int e = 0; e < (RS * PCA_L) / 256; ++e) {
-      const int idx = tid + 256 * e;
-      const int64_t row = s + idx / PCA_L;
-      ys[idx] = row < r1 ? Y[row * PCA_L + idx % PCA_L] : 0.0f;
+    for (int e = 0; e < 2; ++e) {
+      const int r = (tid >> 4) + 16 * e;
+      const bool ok = s + r < r1;
+      double* d = ys + r * PCA_L + 4 * (tid & 15);
+      d[0] = ok ? double(rv[e].x) : 0.0;
+      d[1] = ok ? double(rv[e].y) : 0.0;
+      d[2] = ok ? double(rv[e].z) : 0.0;
+      d[3] = ok ? double(rv[e].w) : 0.0;
     }
     __syncthreads();
-    for (int r = 0; r < RS; ++r) {
-      const double ya = double(ys[r * PCA_L + a]);
+    if (s + RS < r1) load(s + RS);
+#pragma unroll 2
+    for (int t = 0; t < RS / 4; ++t) {
+      const double* yr = ys + (w + 4 * t) * PCA_L;
+      double av[8], bv[8];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[e] = fma(ya, double(ys[r * PCA_L + b0 + e]), acc[e]);
+      for (int i = 0; i < 8; ++i) {
+        av[i] = yr[ia + i];
+        bv[i] = yr[ib + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  for (int v = 0; v < 4; ++v) {
+    if (w == v) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          double& o = sum[(ia + i) * PCA_L + ib + j];
+          o = v == 0 ? acc[i][j] : o + acc[i][j];
+        }
     }
     __syncthreads();
   }
   double* out = part + int64_t(blockIdx.x) * PCA_L * PCA_L;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) out[a * PCA_L + b0 + e] = acc[e];
+  for (int e = tid; e < PCA_L * PCA_L; e += 256) out[e] = sum[e];
 }
 
-// G[e] = sum over the nchunk partials (in order), e < 64 x 64.
-__global__ __launch_bounds__(256) void pca_gram_reduce_kernel(const double* __restrict__ part, int64_t nchunk,
-                                                              double* __restrict__ G) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= PCA_L * PCA_L) return;
-  double s = 0.0;
-  for (int64_t r = 0; r < nchunk; ++r) s += part[r * PCA_L * PCA_L + e];
-  G[e] = s;
+// G[e] = sum over the nchunk partials (eight running sums, added in a fixed
+// order), e < 64 x 64; 64 threads per block.
+__global__ __launch_bounds__(64) void pca_gram_reduce_kernel(const double* __restrict__ part, int64_t nchunk,
+                                                             double* __restrict__ G) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t r = 0;
+  for (; r + 8 <= nchunk; r += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += part[(r + u) * PCA_L * PCA_L + e];
+  for (; r < nchunk; ++r) s[0] += part[r * PCA_L * PCA_L + e];
+  G[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // --- Cholesky G = R^T R (upper R) and R^-1, one block, FP64 ------------------
 
 // shift > 0 adds shift * trace / 64 to the diagonal (the first, shifted pass
-// of CholeskyQR2).  Right-looking: per column, the pivot, the row of R, then
-// the trailing update of the upper triangle in parallel.  Rinv (float,
-// 64 x 64 row-major) is the W of the next product Q = Y Rinv.
+// of CholeskyQR2).  Right-looking: per column j the pivot, row j of R, then
+// the trailing update of the upper triangle.  Thread t owns the entries
+// (t / 64 + 4 u, t % 64), u < 16, of every update; it loads all of them
+// before it stores any, so one LDS round trip serves a whole step.  The
+// inverse: R X = I for all 64 right-hand sides at once, by column-oriented
+// back substitution (per i, row i of X divided by R[i][i], then its multiples
+// taken off the rows above).  Rinv (float, 64 x 64 row-major) is the W of
+// the next product Q = Y Rinv.
 __global__ __launch_bounds__(256) void pca_cholinv_kernel(const double* __restrict__ Gin, double shift,
                                                           float* __restrict__ Rinv) {
+  constexpr int NU = PCA_L * PCA_L / 256;
   __shared__ double A[PCA_L][PCA_L + 1];
   __shared__ double X[PCA_L][PCA_L + 1];
   __shared__ double red[4];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < PCA_L * PCA_L; e += 256) A[e / PCA_L][e % PCA_L] = Gin[e];
+  const int tid = threadIdx.x, r0 = tid >> 6, c = tid & 63;
+  for (int e = tid; e < PCA_L * PCA_L; e += 256) {
+    A[e / PCA_L][e % PCA_L] = Gin[e];
+    X[e / PCA_L][e % PCA_L] = (e / PCA_L == e % PCA_L) ? 1.0 : 0.0;
+  }
   __syncthreads();
   if (shift > 0.0) {
     const double tr = block_sum_d(tid < PCA_L ? A[tid][tid] : 0.0, red);
@@ -362,28 +401,44 @@ __global__ __launch_bounds__(256) void pca_cholinv_kernel(const double* __restri
     __syncthreads();
   }
   for (int j = 0; j < PCA_L; ++j) {
-    if (tid == 0) {
+    // row j of R: every thread of the first wave takes the pivot itself
+    if (tid < PCA_L && tid >= j) {
       const double d = A[j][j];
-      A[j][j] = sqrt(d > 1e-300 ? d : 1e-300);
+      const double rjj = sqrt(d > 1e-300 ? d : 1e-300);
+      const double v = tid == j ? rjj : A[j][tid] / rjj;
+      __builtin_amdgcn_wave_barrier();  // every lane has read A[j][j] before lane j replaces it
+      A[j][tid] = v;
     }
     __syncthreads();
-    if (tid > j && tid < PCA_L) A[j][tid] /= A[j][j];
-    __syncthreads();
-    for (int e = tid; e < PCA_L * PCA_L; e += 256) {
-      const int i = e / PCA_L, c = e % PCA_L;
-      if (i > j && c >= i) A[i][c] -= A[j][i] * A[j][c];
+    double rji[NU], aic[NU];
+    const double rjc = A[j][c];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      rji[u] = A[j][r0 + 4 * u];
+      aic[u] = A[r0 + 4 * u][c];
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int i = r0 + 4 * u;
+      if (i > j && c >= i) A[i][c] = aic[u] - rji[u] * rjc;
     }
     __syncthreads();
   }
-  // R X = I with R the upper triangle of A: row i of X from rows i+1 ..,
-  // one thread per column
   for (int i = PCA_L - 1; i >= 0; --i) {
-    if (tid < PCA_L) {
-      const int c = tid;
-      double v = (i == c) ? 1.0 : 0.0;
-      for (int p = i + 1; p <= c; ++p) v -= A[i][p] * X[p][c];
-      X[i][c] = i <= c ? v / A[i][i] : 0.0;
+    const double xi = X[i][c] / A[i][i];
+    double rpi[NU], xpc[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      rpi[u] = A[r0 + 4 * u][i];
+      xpc[u] = X[r0 + 4 * u][c];
     }
+    __syncthreads();  // row i of X read by every thread before it is replaced
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int p = r0 + 4 * u;
+      if (p < i) X[p][c] = xpc[u] - rpi[u] * xi;
+    }
+    if (r0 == 0) X[i][c] = xi;
     __syncthreads();
   }
   for (int e = tid; e < PCA_L * PCA_L; e += 256) Rinv[e] = float(X[e / PCA_L][e % PCA_L]);
@@ -442,27 +497,47 @@ __global__ __launch_bounds__(256) void pca_jacobi_kernel(const double* __restric
         qq[tid] = q;
       }
       __syncthreads();
-      // rows p, q of A (A <- J^T A)
-      for (int e = tid; e < 32 * PCA_L; e += 256) {
-        const int i = e / PCA_L, j = e % PCA_L;
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], s = sn[i];
-        const double ap = A[p][j], aq = A[q][j];
-        A[p][j] = c * ap - s * aq;
-        A[q][j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns p, q of A and of V (A <- A J, V <- V J)
-      for (int e = tid; e < 32 * PCA_L; e += 256) {
-        const int i = e / PCA_L, j = e % PCA_L;
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], s = sn[i];
-        const double ap = A[j][p], aq = A[j][q];
-        A[j][p] = c * ap - s * aq;
-        A[j][q] = s * ap + c * aq;
-        const double vp = V[j][p], vq = V[j][q];
-        V[j][p] = c * vp - s * vq;
-        V[j][q] = s * vp + c * vq;
+      // A <- J^T A J on the 2 x 2 blocks (rows of pair I, columns of pair J):
+      // the rows rotated first, then the columns, as in the two-pass order;
+      // V <- V J on the columns of every pair.  The blocks and the pairs are
+      // disjoint, so each thread loads all of its entries before it stores.
+      {
+        constexpr int NBK = 32 * 32 / 256, NV = 32 * PCA_L / 256;
+        double blk[NBK][4], vv[NV][2];
+#pragma unroll
+        for (int u = 0; u < NBK; ++u) {
+          const int e = tid + 256 * u, I = e >> 5, J = e & 31;
+          const int p1 = pp[I], q1 = qq[I], p2 = pp[J], q2 = qq[J];
+          blk[u][0] = A[p1][p2];
+          blk[u][1] = A[p1][q2];
+          blk[u][2] = A[q1][p2];
+          blk[u][3] = A[q1][q2];
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          const int e = tid + 256 * u, i = e / PCA_L, j = e % PCA_L;
+          vv[u][0] = V[j][pp[i]];
+          vv[u][1] = V[j][qq[i]];
+        }
+#pragma unroll
+        for (int u = 0; u < NBK; ++u) {
+          const int e = tid + 256 * u, I = e >> 5, J = e & 31;
+          const int p1 = pp[I], q1 = qq[I], p2 = pp[J], q2 = qq[J];
+          const double c1 = cs[I], s1 = sn[I], c2 = cs[J], s2 = sn[J];
+          const double rpp = c1 * blk[u][0] - s1 * blk[u][2], rpq = c1 * blk[u][1] - s1 * blk[u][3];
+          const double rqp = s1 * blk[u][0] + c1 * blk[u][2], rqq = s1 * blk[u][1] + c1 * blk[u][3];
+          A[p1][p2] = c2 * rpp - s2 * rpq;
+          A[p1][q2] = s2 * rpp + c2 * rpq;
+          A[q1][p2] = c2 * rqp - s2 * rqq;
+          A[q1][q2] = s2 * rqp + c2 * rqq;
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          const int e = tid + 256 * u, i = e / PCA_L, j = e % PCA_L;
+          const double c = cs[i], s = sn[i];
+          V[j][pp[i]] = c * vv[u][0] - s * vv[u][1];
+          V[j][qq[i]] = s * vv[u][0] + c * vv[u][1];
+        }
       }
       __syncthreads();
     }
@@ -539,12 +614,24 @@ struct PcaPlan {
   int64_t nchunk_n, nchunk_g, gchunk_max;
 };
 
+// Row blocks of a Gram matrix over m rows: at most PCA_GMAX blocks, each a
+// multiple of 32 rows and at least PCA_GRC rows where m allows.
+struct GramSplit {
+  int64_t nblk, rpb;
+};
+GramSplit gram_split(int64_t m) {
+  int64_t nblk = ceil_div(m, PCA_GRC);
+  if (nblk > PCA_GMAX) nblk = PCA_GMAX;
+  const int64_t rpb = ceil_div(ceil_div(m, nblk), 32) * 32;
+  return {ceil_div(m, rpb), rpb};
+}
+
 PcaPlan pca_plan(int64_t n, int g) {
   PcaPlan L;
   Carve c;
   L.nchunk_n = ceil_div(n, PCA_RC);
   L.nchunk_g = ceil_div(g, PCA_RC);
-  const int64_t gn = ceil_div(n, PCA_GRC), gg = ceil_div(g, PCA_GRC);
+  const int64_t gn = gram_split(n).nblk, gg = gram_split(g).nblk;
   L.gchunk_max = gn > gg ? gn : gg;
   L.o_mpart = c.take(sizeof(double) * size_t(L.nchunk_n) * size_t(g));
   L.o_Ya = c.take(sizeof(float) * size_t(n) * PCA_L);
@@ -607,11 +694,12 @@ int pca_red(const PcaCtx& x, const float* A, int64_t M, int K, const float* mu, 
 
 // G (64 x 64, FP64, in the workspace) = Y^T Y
 int pca_gram(const PcaCtx& x, const float* Y, int64_t m) {
-  const int64_t nch = ceil_div(m, PCA_GRC);
-  hipLaunchKernelGGL(pca_gram_kernel, dim3(unsigned(nch)), dim3(256), 0, x.s, Y, m, x.at<double>(x.L.o_gpart));
+  const GramSplit sp = gram_split(m);
+  hipLaunchKernelGGL(pca_gram_kernel, dim3(unsigned(sp.nblk)), dim3(256), 0, x.s, Y, m, sp.rpb,
+                     x.at<double>(x.L.o_gpart));
   TSNE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(pca_gram_reduce_kernel, dim3(PCA_L * PCA_L / 256), dim3(256), 0, x.s, x.at<double>(x.L.o_gpart),
-                     nch, x.at<double>(x.L.o_G));
+  hipLaunchKernelGGL(pca_gram_reduce_kernel, dim3(PCA_L * PCA_L / 64), dim3(64), 0, x.s, x.at<double>(x.L.o_gpart),
+                     sp.nblk, x.at<double>(x.L.o_G));
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
 }
