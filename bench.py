@@ -10,8 +10,9 @@ around every 10th launch of the all-pairs repulsion kernel: they give the
 dominant kernel's average per-launch time for the roofline.  Outside the timed region: the BF16-MFMA vs FP32 kNN build
 comparison, and the CPU-baseline leg (the FP64 oracle timed on a bounded
 sample of the same workload, which also yields the error statistics), the
-KL autograd timing, and the interpolated (FFT) gradient timed against the
-exact one at the C5 point count.
+KL autograd timing, the interpolated (FFT) gradient timed against the
+exact one at the C5 point count, and the PCA that produces the embedding's
+input (200k cells x 2000 genes, 50 components, 2 power iterations).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 """
@@ -46,6 +47,9 @@ def parse():
                     help="point count of the KL autograd forward/backward timing (0: skip)")
     ap.add_argument("--fft-n", type=int, default=1_000_000,
                     help="point count of the interpolated-vs-exact gradient comparison (C5 shape; 0: skip)")
+    ap.add_argument("--pca-n", type=int, default=200_000,
+                    help="cells of the PCA timing (tsne_pca, k = 50 of 64, q = 2; 0: skip)")
+    ap.add_argument("--pca-g", type=int, default=2000, help="genes of the PCA timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -268,6 +272,20 @@ def main():
         del Xd, Yd, vd, Pd, idd, d2d
         progress(f"autograd timing at n={nd} done")
 
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            out = fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts)), out
+
     # --- interpolated repulsion (tsne_kl_grad_fft) against the exact pass ---
     interp = {}
     if args.fft_n:
@@ -281,21 +299,6 @@ def main():
         std = 30.0  # a spread embedding (late-iteration scale) of the c5 point count
         Yf = torch.from_numpy(synth.random_embedding(nf, std, 4242)).to(dev)
         wse, wsi = api.Workspace(), api.Workspace()
-
-        def timed(fn, reps):
-            fn()
-            torch.cuda.synchronize()
-            ts = []
-            for _ in range(reps):
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                out = fn()
-                b.record(stream)
-                torch.cuda.synchronize()
-                ts.append(a.elapsed_time(b))
-            return float(np.median(ts)), out
-
         te, (ge, Ze, _, _) = timed(lambda: api.kl_grad(Yf, Pf, 1.0, want_Z=True, ws=wse), 3)
         tf, (gf, Zf, _) = timed(lambda: api.kl_grad_fft(Yf, Pf, 1.0, want_Z=True, ws=wsi), 10)
         interp = {"n": nf, "nnz": int(Pf.nnz), "embedding": f"N(0, {std:g}^2 I), float32, seed 4242",
@@ -305,6 +308,32 @@ def main():
                   "Z_rel_err_vs_exact": abs(Zf.item() - Ze.item()) / Ze.item()}
         del Yf, Pf, ge, gf, wse, wsi, wsf
         progress(f"interpolated gradient at n={nf} done")
+
+    # --- PCA (tsne_pca): randomized truncated SVD of a cells x genes matrix ---
+    pca = {}
+    if args.pca_n:
+        npc, gpc, kpc, qpc = args.pca_n, args.pca_g, 50, 2
+        Xp = torch.from_numpy(synth.make_expression(npc, gpc, 2024)).to(dev)
+        Om = torch.from_numpy(synth.make_omega(gpc, 2025)).to(dev)
+        wsp = api.Workspace()
+        tp, (sc, comp, sv, mu) = timed(lambda: api.pca(Xp, kpc, Om, qpc, ws=wsp), 5)
+        passes = 2 + 2 * qpc  # X products: the range finder, 2 per power iteration, B
+        flops = passes * 2.0 * npc * gpc * api.PCA_SUBSPACE
+        # checks that need no oracle: orthonormal components, and the scores
+        # equal to the centred rows projected on them (FP64, a sample of rows)
+        cd = comp.double()
+        orth_err = float((cd @ cd.T - torch.eye(kpc, dtype=torch.float64, device=dev)).abs().max())
+        rows = torch.from_numpy(np.random.default_rng(11).choice(npc, 2000, replace=False)).to(dev)
+        proj = (Xp[rows].double() - mu.double()) @ cd.T
+        proj_err = float(torch.linalg.norm(sc[rows].double() - proj) / torch.linalg.norm(proj))
+        pca = {"n": npc, "g": gpc, "k": kpc, "q": qpc, "subspace": api.PCA_SUBSPACE,
+               "data": "make_expression: 64 latent programmes, singular values 100 to 1, noise 0.05, offset 2",
+               "ms": tp, "x_passes": passes, "x_product_tflops": flops / (tp * 1e-3) / 1e12,
+               "x_read_tb_s": passes * npc * gpc * 4 / (tp * 1e-3) / 1e12,
+               "components_orthonormality_max_err": orth_err, "scores_projection_rel_err": proj_err,
+               "singular_values_head": [float(v) for v in sv[:5].cpu()]}
+        del Xp, Om, sc, comp, sv, mu, wsp
+        progress(f"pca at {npc} x {gpc} done")
 
     # --- CPU baseline: the FP64 oracle on a bounded sample ------------------
     cpu = None
@@ -409,6 +438,7 @@ def main():
         "knn_build_s": {f"{w.knn}_in_step": knn_fp32_s, **knn_cmp},
         "kl_autograd": diff,
         "interpolated_gradient": interp,
+        "pca": pca,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "errors_vs_fp64": errors,
