@@ -22,6 +22,15 @@
  *            improved visualization of single-cell RNA-seq data":
  *            repulsive sums by polynomial interpolation on equispaced
  *            nodes and FFT convolution (the approximate form below).
+ *   [MHM18]  McInnes, Healy & Melville, "UMAP: Uniform Manifold
+ *            Approximation and Projection for Dimension Reduction",
+ *            arXiv:1802.03426 (2018): local fuzzy simplicial sets and their
+ *            fuzzy union (Sec. 3.1), the fitted low-dimensional similarity
+ *            and the layout by SGD with negative sampling (Sec. 3.2) --
+ *            the tsne_umap_* entry points.
+ *   [SLF14]  Steele, Lea & Flood, "Fast splittable pseudorandom number
+ *            generators", OOPSLA 2014: SplitMix64, the counter-based
+ *            generator of UMAP's negative samples.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -327,6 +336,63 @@ int tsne_kl_forward(int32_t dtype, const void* Y, int64_t n, const int64_t* row_
 int tsne_kl_backward(int32_t dtype, const void* Y, int64_t n, const int64_t* row_ptr, const int32_t* col,
                      const void* val, const int32_t* tpos, const void* gC, void* dY, void* dP, void* workspace,
                      size_t* workspace_bytes, void* stream);
+
+/*
+ * UMAP on the kNN graph [MHM18].  The neighbour lists are those of tsne_knn
+ * (self excluded, squared Euclidean distances); the embedding is 2-D.
+ *
+ * tsne_umap_fit_ab -- host only (no device work): a, b of the similarity
+ * Phi(d) = 1 / (1 + a d^2b) fitted by least squares (Levenberg-Marquardt
+ * from a = b = 1) to Psi(d) = 1 for d <= min_dist, exp(-(d - min_dist))
+ * beyond, over the 300 points d = 3 m / 299 [MHM18] Sec. 3.2.
+ *   min_dist  in [0, 3).  a, b host doubles out.
+ *
+ * tsne_umap_weights -- the local fuzzy simplicial set of every row [MHM18]
+ * Sec. 3.1: with d_j = sqrt(d2_j) (FP64), rho = the smallest positive d_j
+ * (0 if none), sigma the root of sum_j exp(-max(0, d_j - rho) / sigma) =
+ * log2(k) (FP64 bisection; sigma >= 1e-3 mean_j d_j, or 1e-3 when every
+ * d_j is 0, and sigma stays at that floor when the floor already meets the
+ * target), w_j = exp(-max(0, d_j - rho) / sigma).
+ *   nbr_d2    [n][k] float: squared distances of the neighbour lists.
+ *   rho, sigma [n] float out; w [n][k] float out (row-aligned with nbr_d2).
+ *   n >= 1, 1 <= k <= TSNE_MAX_K.  One launch, no workspace.
+ *
+ * tsne_umap_fuzzy_union -- B = A + A^T - A o A^T [MHM18] Sec. 3.1 on the
+ * union of the kNN patterns: the arguments, outputs, workspace, limits and
+ * error behaviour of tsne_symmetrize with the directed weights w in place
+ * of P_cond; entry (i, j) holds (a + a') - a a' with a = w_{i->j}, a' =
+ * w_{j->i} (0 when absent), the same FP32 value in rows i and j.
+ *
+ * tsne_umap_layout -- epochs [epoch_begin, epoch_end) of the layout
+ * [MHM18] Sec. 3.2, in place on Y.  Epoch t: learning rate alpha =
+ * alpha0 (1 - t / n_epochs); stored entry e = (i, j) of the graph is
+ * sampled when floor((t + 1) r_e) > floor(t r_e) with r_e = val_e / max val
+ * (FP32 division and products), so it is sampled floor(n_epochs r_e) times
+ * in all.  A sampled entry adds alpha clip(c_a (y_i - y_j)) to y_i and
+ * subtracts it from y_j, c_a = -2ab d^2(b-1) / (1 + a d^2b), then for
+ * p < neg_rate the vertex c = ((z >> 32) n) >> 32 of the SplitMix64 output z
+ * [SLF14] for seed and counter (t nnz + e) neg_rate + p (skipped if c = i)
+ * adds alpha clip(c_r (y_i - y_c)) to y_i, c_r = 2b / ((1e-3 + d^2)(1 +
+ * a d^2b)); no step at distance 0; clip to [-4, 4] per coordinate.  All
+ * steps of an epoch are evaluated at the epoch's starting Y and summed in
+ * 64-bit fixed point (2^-32), so an epoch is exact in its sums and bitwise
+ * reproducible; epochs run in order on `stream`.
+ *   Y         [n][2] float, in place.  2 <= n < 2^31.
+ *   row_ptr, col, val  CSR graph ([n+1] int64, [nnz] int32, [nnz] float),
+ *             values >= 0 with a positive maximum (the output of
+ *             tsne_umap_fuzzy_union); nnz = row_ptr[n] >= 1.
+ *   a, b > 0; alpha0 >= 0; 0 <= neg_rate <= 64; n_epochs >= 1;
+ *   0 <= epoch_begin <= epoch_end <= n_epochs.  seed: the generator's seed.
+ *   Workspace: 16 n bytes + 1 KiB.
+ */
+int tsne_umap_fit_ab(double min_dist, double* a, double* b);
+int tsne_umap_weights(const float* nbr_d2, int64_t n, int32_t k, float* rho, float* sigma, float* w, void* stream);
+int tsne_umap_fuzzy_union(const int32_t* nbr_idx, const float* w, int64_t n, int32_t k, int64_t* row_ptr,
+                          int32_t* col, float* val, int32_t* tpos, int64_t* nnz, void* workspace,
+                          size_t* workspace_bytes, void* stream);
+int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val, int64_t nnz,
+                     double a, double b, double alpha0, int32_t neg_rate, int32_t n_epochs, int32_t epoch_begin,
+                     int32_t epoch_end, uint64_t seed, void* workspace, size_t* workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ from ._lib import check
 KLGRAD_FLOPS_PER_ORDERED_PAIR = 8.5
 
 __all__ = ["knn", "calibrate_P", "symmetrize", "kl_grad", "step", "optimize", "kl_forward", "kl_backward",
-           "SparseP", "Workspace"]
+           "umap_fit_ab", "umap_weights", "umap_fuzzy_union", "umap_layout", "SparseP", "Workspace"]
 
 
 def _ptr(t):
@@ -306,3 +306,64 @@ def kl_backward(Y: torch.Tensor, val: torch.Tensor, P: SparseP, gC: torch.Tensor
                         (dt, _ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(val), _ptr(P.tpos), _ptr(gC), _ptr(dY),
                          _ptr(dP)), (_stream(dev),), dev, ws)
     return dY, dP
+
+
+# --- UMAP on the kNN graph -------------------------------------------------------
+
+def umap_fit_ab(min_dist: float = 0.5):
+    """(a, b) of Phi(d) = 1 / (1 + a d^2b) fitted to the min_dist curve (host computation in the library)."""
+    a, b = C.c_double(0.0), C.c_double(0.0)
+    check("tsne_umap_fit_ab", _lib.load().tsne_umap_fit_ab(float(min_dist), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def umap_weights(nbr_d2: torch.Tensor):
+    """Smoothed kNN weights of every row.  Returns (rho [n], sigma [n], w [n, k]) float32."""
+    _req(nbr_d2, "nbr_d2", torch.float32)
+    n, k = nbr_d2.shape
+    dev = nbr_d2.device
+    rho = torch.empty(n, dtype=torch.float32, device=dev)
+    sigma = torch.empty(n, dtype=torch.float32, device=dev)
+    w = torch.empty((n, k), dtype=torch.float32, device=dev)
+    check("tsne_umap_weights", _lib.load().tsne_umap_weights(_ptr(nbr_d2), n, k, _ptr(rho), _ptr(sigma), _ptr(w),
+                                                             _stream(dev)))
+    return rho, sigma, w
+
+
+def umap_fuzzy_union(nbr_idx: torch.Tensor, w: torch.Tensor, ws: Workspace | None = None) -> SparseP:
+    """B = A + A^T - A o A^T on the union pattern as CSR (one host sync to read nnz; no tpos)."""
+    _req(nbr_idx, "nbr_idx", torch.int32)
+    n, k = nbr_idx.shape
+    _req(w, "w", torch.float32, (n, k))
+    dev = nbr_idx.device
+    cap = 2 * n * k
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(cap, dtype=torch.int32, device=dev)
+    val = torch.empty(cap, dtype=torch.float32, device=dev)
+    nnz = torch.empty(1, dtype=torch.int64, device=dev)
+    L = _lib.load()
+    _run_with_workspace("tsne_umap_fuzzy_union", L.tsne_umap_fuzzy_union,
+                        (_ptr(nbr_idx), _ptr(w), n, k, _ptr(row_ptr), _ptr(col), _ptr(val), None, _ptr(nnz)),
+                        (_stream(dev),), dev, ws)
+    m = int(nnz.item())
+    if m < 0:
+        raise ValueError("tsne_umap_fuzzy_union: a neighbour list holds an out-of-range index, self or a repeat")
+    return SparseP(row_ptr, col[:m], val[:m], None, n)
+
+
+def umap_layout(Y: torch.Tensor, G: SparseP, a: float, b: float, n_epochs: int, alpha0: float = 1.0,
+                neg_rate: int = 5, seed: int = 0, epochs: tuple[int, int] | None = None,
+                ws: Workspace | None = None) -> torch.Tensor:
+    """Epochs [t0, t1) of the layout (all n_epochs by default), in place on Y [n, 2] float32."""
+    _req(Y, "Y", torch.float32)
+    n = Y.shape[0]
+    if Y.shape != (n, 2) or G.n != n:
+        raise ValueError("Y must be [n, 2] matching the graph")
+    t0, t1 = (0, n_epochs) if epochs is None else epochs
+    dev = Y.device
+    L = _lib.load()
+    _run_with_workspace("tsne_umap_layout", L.tsne_umap_layout,
+                        (_ptr(Y), n, _ptr(G.row_ptr), _ptr(G.col), _ptr(G.val), G.nnz, float(a), float(b),
+                         float(alpha0), int(neg_rate), int(n_epochs), int(t0), int(t1), C.c_uint64(seed)),
+                        (_stream(dev),), dev, ws, key=("umap_layout", n))
+    return Y

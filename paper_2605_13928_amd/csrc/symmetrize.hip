@@ -17,6 +17,9 @@
 //   7. tpos by binary search of i in row col[e]
 // Entry values are (p_{j|i} + p_{i|j}) / (2n) in row i and
 // (p_{i|j} + p_{j|i}) / (2n) in row j: the same FP32 sum, so P = P^T bitwise.
+// tsne_umap_fuzzy_union runs the same steps with the probabilistic t-conorm
+// b = (a + a') - a a' of the two directed weights in step 6 (McInnes, Healy &
+// Melville 2018, Sec. 3.1), symmetric bitwise for the same reason.
 #include "common.hpp"
 #include "scan.hpp"
 
@@ -242,6 +245,15 @@ __global__ __launch_bounds__(256) void sym_union_count_kernel(int64_t n, int k, 
   if (lane == 0) ucount[row] = int64_t(k) + len - dups;
 }
 
+// Combined value of an entry from its out-weight u and in-weight v (0 when
+// absent): MODE 0 the t-SNE average (u + v) / 2n, MODE 1 the fuzzy union.
+template <int MODE>
+__device__ __forceinline__ float sym_combine(float u, float v, float two_n) {
+  if (MODE == 0) return (u + v) / two_n;
+  return (u + v) - u * v;
+}
+
+template <int MODE>
 __global__ __launch_bounds__(256) void sym_write_kernel(int64_t n, int k, const int32_t* __restrict__ o_col,
                                                         const float* __restrict__ o_val,
                                                         const int64_t* __restrict__ in_ptr,
@@ -276,7 +288,7 @@ __global__ __launch_bounds__(256) void sym_write_kernel(int64_t n, int k, const 
     if (a < k) {
       const int64_t pos = a + lb - (run + __popcll(m & lt_mask));
       col[rp + pos] = c;
-      val[rp + pos] = (outv[a] + (dup ? inv[lb] : 0.0f)) / two_n;
+      val[rp + pos] = sym_combine<MODE>(outv[a], dup ? inv[lb] : 0.0f, two_n);
     }
     run += __popcll(m);
   }
@@ -296,7 +308,7 @@ __global__ __launch_bounds__(256) void sym_write_kernel(int64_t n, int k, const 
     if (b < len && !dup) {
       const int64_t pos = b + lb - (run + __popcll(m & lt_mask));
       col[rp + pos] = c;
-      val[rp + pos] = (0.0f + inv[b]) / two_n;
+      val[rp + pos] = sym_combine<MODE>(0.0f, inv[b], two_n);
     }
     run += __popcll(m);
   }
@@ -350,10 +362,14 @@ struct SymLayout {
 
 }  // namespace tsne
 
-extern "C" int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64_t n, int32_t k, int64_t* row_ptr,
-                               int32_t* col, float* val, int32_t* tpos, int64_t* nnz, void* workspace,
-                               size_t* workspace_bytes, void* stream) {
-  using namespace tsne;
+namespace tsne {
+
+// The union of the kNN patterns as CSR with the MODE combination of the two
+// directed values (steps 1-7 above).
+template <int MODE>
+int symmetrize_impl(const int32_t* nbr_idx, const float* P_cond, int64_t n, int32_t k, int64_t* row_ptr,
+                    int32_t* col, float* val, int32_t* tpos, int64_t* nnz, void* workspace, size_t* workspace_bytes,
+                    void* stream) {
   if (!nbr_idx || !P_cond || !row_ptr || !col || !val || !nnz || n < 2 || k < 1 || k >= n) return TSNE_ERR_INVALID_ARG;
   if (k > TSNE_MAX_K) return TSNE_ERR_UNSUPPORTED;
   if (n > (int64_t(1) << 30)) return TSNE_ERR_UNSUPPORTED;  // 2 n k must fit int32 positions in tpos
@@ -396,7 +412,8 @@ extern "C" int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int6
   hipLaunchKernelGGL(sym_union_count_kernel, g_rows, b, 0, s, n, k, o_col, in_ptr, s_src, ucount);
   TSNE_CHECK_LAUNCH();
   if ((rc = exclusive_scan<int64_t>(ucount, n, row_ptr, bsum, s))) return rc;
-  hipLaunchKernelGGL(sym_write_kernel, g_rows, b, 0, s, n, k, o_col, o_val, in_ptr, s_src, s_val, row_ptr, col, val);
+  hipLaunchKernelGGL(sym_write_kernel<MODE>, g_rows, b, 0, s, n, k, o_col, o_val, in_ptr, s_src, s_val, row_ptr, col,
+                     val);
   TSNE_CHECK_LAUNCH();
   if (tpos) {
     hipLaunchKernelGGL(sym_tpos_kernel, g_rows, b, 0, s, n, row_ptr, col, tpos);
@@ -405,4 +422,19 @@ extern "C" int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int6
   hipLaunchKernelGGL(sym_nnz_kernel, dim3(1), dim3(64), 0, s, row_ptr, n, err, nnz);
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
+}
+
+}  // namespace tsne
+
+extern "C" int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64_t n, int32_t k, int64_t* row_ptr,
+                               int32_t* col, float* val, int32_t* tpos, int64_t* nnz, void* workspace,
+                               size_t* workspace_bytes, void* stream) {
+  return tsne::symmetrize_impl<0>(nbr_idx, P_cond, n, k, row_ptr, col, val, tpos, nnz, workspace, workspace_bytes,
+                                  stream);
+}
+
+extern "C" int tsne_umap_fuzzy_union(const int32_t* nbr_idx, const float* w, int64_t n, int32_t k, int64_t* row_ptr,
+                                     int32_t* col, float* val, int32_t* tpos, int64_t* nnz, void* workspace,
+                                     size_t* workspace_bytes, void* stream) {
+  return tsne::symmetrize_impl<1>(nbr_idx, w, n, k, row_ptr, col, val, tpos, nnz, workspace, workspace_bytes, stream);
 }

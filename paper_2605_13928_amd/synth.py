@@ -163,6 +163,12 @@ def random_knn_graph(n: int, k: int, seed: int, scale: float = 100.0):
     return np.ascontiguousarray(idx, dtype=np.int32), np.ascontiguousarray(d2, dtype=np.float32)
 
 
+def umap_init(n: int, seed: int, half_width: float = 10.0) -> np.ndarray:
+    """A random 2-D starting layout for UMAP: uniform on [-half_width, half_width]^2, float32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-half_width, half_width, size=(n, 2)).astype(np.float32)
+
+
 def make_expression(n: int, g: int, seed: int, latent: int = 64, top: float = 100.0, bottom: float = 1.0,
                     noise: float = 0.05, offset: float = 2.0) -> np.ndarray:
     """Expression-like X [n, g] float32 (the input of the PCA step): cells with

@@ -144,3 +144,49 @@ def test_invalid_arguments_rejected(L):
     # differentiation form
     assert ws_query(L.tsne_kl_forward, 5, fake, 64, fake, fake, fake, fake, NULL)[0] == IA  # dtype
     assert ws_query(L.tsne_kl_backward, 0, fake, 64, fake, fake, fake, NULL, fake, fake, NULL)[0] == IA  # tpos
+
+
+def test_umap_arguments_and_workspace(L):
+    fake = C.c_void_p(0x1000)
+    IA, UN = _lib.TSNE_ERR_INVALID_ARG, _lib.TSNE_ERR_UNSUPPORTED
+    wt = L.tsne_umap_weights
+    assert wt(NULL, 10, 15, fake, fake, fake, NULL) == IA
+    assert wt(fake, 0, 15, fake, fake, fake, NULL) == IA and wt(fake, 10, 0, fake, fake, fake, NULL) == IA
+    assert wt(fake, 10, 300, fake, fake, fake, NULL) == UN
+    assert wt(fake, 10, 15, fake, NULL, fake, NULL) == IA
+    fu = L.tsne_umap_fuzzy_union
+    rc, need = ws_query(fu, fake, fake, 1000, 15, fake, fake, fake, NULL, fake)
+    rc_s, need_s = ws_query(L.tsne_symmetrize, fake, fake, 1000, 15, fake, fake, fake, NULL, fake)
+    assert rc == 0 and need == need_s
+    assert ws_query(fu, fake, fake, 100, 100, fake, fake, fake, NULL, fake)[0] == IA
+    lay = L.tsne_umap_layout
+
+    def lq(Y=fake, n=1000, nnz=20000, a=1.5, b=0.9, alpha=1.0, neg=5, ne=200, t0=0, t1=200):
+        return ws_query(lay, Y, n, fake, fake, fake, nnz, C.c_double(a), C.c_double(b), C.c_double(alpha), neg, ne,
+                        t0, t1, C.c_uint64(7))
+
+    rc, need = lq()
+    assert rc == 0 and 16 * 1000 <= need <= 16 * 1000 + 4096
+    assert lq(Y=NULL)[0] == IA and lq(n=1)[0] == IA and lq(nnz=0)[0] == IA
+    assert lq(a=0.0)[0] == IA and lq(b=-1.0)[0] == IA and lq(alpha=-0.1)[0] == IA
+    assert lq(neg=-1)[0] == IA and lq(neg=65)[0] == IA and lq(ne=0)[0] == IA
+    assert lq(t0=5, t1=4)[0] == IA and lq(t1=201)[0] == IA and lq(t0=-1)[0] == IA
+    assert lq(t0=200, t1=200)[0] == 0
+    assert lq(n=1 << 31)[0] == UN
+    a, b = C.c_double(0), C.c_double(0)
+    assert L.tsne_umap_fit_ab(C.c_double(-0.1), C.byref(a), C.byref(b)) == IA
+    assert L.tsne_umap_fit_ab(C.c_double(3.0), C.byref(a), C.byref(b)) == IA
+    assert L.tsne_umap_fit_ab(C.c_double(0.1), NULL, C.byref(b)) == IA
+
+
+@pytest.mark.parametrize("min_dist", [0.0, 0.1, 0.5, 1.0])
+def test_umap_fit_ab_matches_oracle(L, min_dist):
+    # host-only entry point: the library's Levenberg-Marquardt fit against
+    # the oracle's (scipy curve_fit) on the same least-squares problem
+    from oracle import umap as U
+
+    a, b = C.c_double(0), C.c_double(0)
+    assert L.tsne_umap_fit_ab(C.c_double(min_dist), C.byref(a), C.byref(b)) == 0
+    oa, ob = U.fit_ab(min_dist)
+    assert abs(a.value - oa) <= 1e-7 * oa and abs(b.value - ob) <= 1e-7 * ob, (a.value, b.value, oa, ob)
+    assert U.fit_objective(a.value, b.value, min_dist) <= U.fit_objective(oa, ob, min_dist) * (1 + 1e-12)
