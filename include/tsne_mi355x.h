@@ -381,9 +381,18 @@ int tsne_kl_backward(int32_t dtype, const void* Y, int64_t n, const int64_t* row
  *   row_ptr, col, val  CSR graph ([n+1] int64, [nnz] int32, [nnz] float),
  *             values >= 0 with a positive maximum (the output of
  *             tsne_umap_fuzzy_union); nnz = row_ptr[n] >= 1.
+ *   symmetric 1: the caller guarantees a symmetric pattern with equal FP32
+ *             values in (i, j) and (j, i) (true of tsne_umap_fuzzy_union's
+ *             output); then each vertex takes twice its own attractive
+ *             steps instead of receiving the reverse entries' steps -- the
+ *             same value bit for bit -- and the epoch scatters nothing.
+ *             0: any graph; the steps into y_j are scattered with 64-bit
+ *             integer atomics.  Both give identical results on a symmetric
+ *             graph; 1 on a graph that is not symmetric gives undefined
+ *             results (not those stated above).
  *   a, b > 0; alpha0 >= 0; 0 <= neg_rate <= 64; n_epochs >= 1;
  *   0 <= epoch_begin <= epoch_end <= n_epochs.  seed: the generator's seed.
- *   Workspace: 16 n bytes + 1 KiB.
+ *   Workspace: 24 n bytes + 1 KiB.
  */
 int tsne_umap_fit_ab(double min_dist, double* a, double* b);
 int tsne_umap_weights(const float* nbr_d2, int64_t n, int32_t k, float* rho, float* sigma, float* w, void* stream);
@@ -391,8 +400,9 @@ int tsne_umap_fuzzy_union(const int32_t* nbr_idx, const float* w, int64_t n, int
                           int32_t* col, float* val, int32_t* tpos, int64_t* nnz, void* workspace,
                           size_t* workspace_bytes, void* stream);
 int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val, int64_t nnz,
-                     double a, double b, double alpha0, int32_t neg_rate, int32_t n_epochs, int32_t epoch_begin,
-                     int32_t epoch_end, uint64_t seed, void* workspace, size_t* workspace_bytes, void* stream);
+                     int32_t symmetric, double a, double b, double alpha0, int32_t neg_rate, int32_t n_epochs,
+                     int32_t epoch_begin, int32_t epoch_end, uint64_t seed, void* workspace, size_t* workspace_bytes,
+                     void* stream);
 
 #ifdef __cplusplus
 }

@@ -57,8 +57,8 @@ SIGNATURES = {
     "tsne_umap_fit_ab": (C.c_int, [C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "tsne_umap_weights": (C.c_int, [_p, _i64, _i32, _p, _p, _p, _p]),
     "tsne_umap_fuzzy_union": (C.c_int, [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _p, _szp, _p]),
-    "tsne_umap_layout": (C.c_int, [_p, _i64, _p, _p, _p, _i64, C.c_double, C.c_double, C.c_double, _i32, _i32, _i32,
-                                   _i32, C.c_uint64, _p, _szp, _p]),
+    "tsne_umap_layout": (C.c_int, [_p, _i64, _p, _p, _p, _i64, _i32, C.c_double, C.c_double, C.c_double, _i32, _i32,
+                                   _i32, _i32, C.c_uint64, _p, _szp, _p]),
 }
 
 _lib = None

@@ -352,9 +352,11 @@ def umap_fuzzy_union(nbr_idx: torch.Tensor, w: torch.Tensor, ws: Workspace | Non
 
 
 def umap_layout(Y: torch.Tensor, G: SparseP, a: float, b: float, n_epochs: int, alpha0: float = 1.0,
-                neg_rate: int = 5, seed: int = 0, epochs: tuple[int, int] | None = None,
+                neg_rate: int = 5, seed: int = 0, epochs: tuple[int, int] | None = None, symmetric: bool = True,
                 ws: Workspace | None = None) -> torch.Tensor:
-    """Epochs [t0, t1) of the layout (all n_epochs by default), in place on Y [n, 2] float32."""
+    """Epochs [t0, t1) of the layout (all n_epochs by default), in place on Y [n, 2] float32.
+    symmetric=True asserts a symmetric graph with equal values in (i, j) and (j, i), as
+    umap_fuzzy_union returns; False handles any graph."""
     _req(Y, "Y", torch.float32)
     n = Y.shape[0]
     if Y.shape != (n, 2) or G.n != n:
@@ -363,7 +365,8 @@ def umap_layout(Y: torch.Tensor, G: SparseP, a: float, b: float, n_epochs: int, 
     dev = Y.device
     L = _lib.load()
     _run_with_workspace("tsne_umap_layout", L.tsne_umap_layout,
-                        (_ptr(Y), n, _ptr(G.row_ptr), _ptr(G.col), _ptr(G.val), G.nnz, float(a), float(b),
+                        (_ptr(Y), n, _ptr(G.row_ptr), _ptr(G.col), _ptr(G.val), G.nnz, int(bool(symmetric)), float(a),
+                         float(b),
                          float(alpha0), int(neg_rate), int(n_epochs), int(t0), int(t1), C.c_uint64(seed)),
                         (_stream(dev),), dev, ws, key=("umap_layout", n))
     return Y

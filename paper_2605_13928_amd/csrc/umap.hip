@@ -198,14 +198,77 @@ __global__ __launch_bounds__(256) void umap_apply_kernel(float2* __restrict__ Y,
   D[2 * i + 1] = 0ull;
 }
 
+// Epoch t on a symmetric graph (pattern and values, as the fuzzy union
+// writes them): entries (i, j) and (j, i) hold the same FP32 value, so they
+// are sampled in the same epochs, and the step that entry (j, i) applies to
+// y_i is bitwise equal to y_i's own step for (i, j) (the squared distance
+// is the same, c_a is symmetric, and clip is odd).  Each vertex therefore
+// takes twice its own attractive steps plus its negatives, and nothing is
+// scattered: one thread per row reads Y_in and writes Y_out, with the same
+// fixed-point sums -- the result equals the scattering path's bit for bit.
+__global__ __launch_bounds__(256) void umap_epoch_sym_kernel(const float2* __restrict__ Yin,
+                                                             float2* __restrict__ Yout, int64_t n,
+                                                             const int64_t* __restrict__ row_ptr,
+                                                             const int32_t* __restrict__ col,
+                                                             const float* __restrict__ val, int64_t nnz,
+                                                             const float* __restrict__ wmax, float a, float b,
+                                                             float alpha, int neg_rate, uint64_t seed, int t) {
+  const int64_t i = gtid();
+  if (i >= n) return;
+  const float rmax = *wmax;
+  const float t0 = float(t), t1 = float(t + 1);
+  const float2 yi = Yin[i];
+  const float cab = -2.0f * a * b, c2b = 2.0f * b;
+  long long ax = 0, ay = 0;
+  const int64_t e1 = row_ptr[i + 1];
+  for (int64_t e = row_ptr[i]; e < e1; ++e) {
+    const float r = __fdiv_rn(val[e], rmax);
+    if (!(floorf(t1 * r) > floorf(t0 * r))) continue;
+    const float2 yj = Yin[col[e]];
+    const float dx = yi.x - yj.x, dy = yi.y - yj.y;
+    const float d2 = dx * dx + dy * dy;
+    if (d2 > 0.0f) {
+      const float pb = powf(d2, b);
+      const float c = cab * (pb / d2) / (1.0f + a * pb);
+      ax += 2 * umap_fx(alpha * umap_clip(c * dx));
+      ay += 2 * umap_fx(alpha * umap_clip(c * dy));
+    }
+    const uint64_t base = (uint64_t(t) * uint64_t(nnz) + uint64_t(e)) * uint64_t(neg_rate);
+    for (int p = 0; p < neg_rate; ++p) {
+      const uint64_t z = splitmix64(seed, base + uint64_t(p));
+      const int64_t c = int64_t(((z >> 32) * uint64_t(n)) >> 32);
+      if (c == i) continue;
+      const float2 yc = Yin[c];
+      const float ex = yi.x - yc.x, ey = yi.y - yc.y;
+      const float q2 = ex * ex + ey * ey;
+      if (q2 > 0.0f) {
+        const float cr = c2b / ((UMAP_EPS + q2) * (1.0f + a * powf(q2, b)));
+        ax += umap_fx(alpha * umap_clip(cr * ex));
+        ay += umap_fx(alpha * umap_clip(cr * ey));
+      }
+    }
+  }
+  float2 y = yi;
+  y.x += float(double(ax) * (1.0 / 4294967296.0));
+  y.y += float(double(ay) * (1.0 / 4294967296.0));
+  Yout[i] = y;
+}
+
+__global__ __launch_bounds__(256) void umap_copy_kernel(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                        int64_t n) {
+  const int64_t i = gtid();
+  if (i < n) dst[i] = src[i];
+}
+
 struct UmapLayout {
-  size_t o_part, o_wmax, o_D, bytes;
+  size_t o_part, o_wmax, o_D, o_Y, bytes;
   static UmapLayout make(int64_t n) {
     UmapLayout L;
     Carve c;
     L.o_part = c.take(sizeof(float) * UMAP_RED_BLOCKS);
     L.o_wmax = c.take(sizeof(float));
     L.o_D = c.take(sizeof(unsigned long long) * 2 * size_t(n));
+    L.o_Y = c.take(sizeof(float2) * size_t(n));
     L.bytes = c.off;
     return L;
   }
@@ -293,13 +356,14 @@ extern "C" int tsne_umap_weights(const float* nbr_d2, int64_t n, int32_t k, floa
 }
 
 extern "C" int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
-                                int64_t nnz, double a, double b, double alpha0, int32_t neg_rate, int32_t n_epochs,
-                                int32_t epoch_begin, int32_t epoch_end, uint64_t seed, void* workspace,
-                                size_t* workspace_bytes, void* stream) {
+                                int64_t nnz, int32_t symmetric, double a, double b, double alpha0, int32_t neg_rate,
+                                int32_t n_epochs, int32_t epoch_begin, int32_t epoch_end, uint64_t seed,
+                                void* workspace, size_t* workspace_bytes, void* stream) {
   using namespace tsne;
   if (!Y || !row_ptr || !col || !val || n < 2 || nnz < 1) return TSNE_ERR_INVALID_ARG;
   if (!(a > 0.0) || !(b > 0.0) || !(alpha0 >= 0.0) || neg_rate < 0 || neg_rate > UMAP_MAX_NEG) return TSNE_ERR_INVALID_ARG;
   if (n_epochs < 1 || epoch_begin < 0 || epoch_begin > epoch_end || epoch_end > n_epochs) return TSNE_ERR_INVALID_ARG;
+  if (symmetric != 0 && symmetric != 1) return TSNE_ERR_INVALID_ARG;
   if (n >= (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
   const UmapLayout L = UmapLayout::make(n);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
@@ -308,8 +372,9 @@ extern "C" int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, con
   float* part = reinterpret_cast<float*>(ws + L.o_part);
   float* wmax = reinterpret_cast<float*>(ws + L.o_wmax);
   unsigned long long* D = reinterpret_cast<unsigned long long*>(ws + L.o_D);
+  float2* Yb = reinterpret_cast<float2*>(ws + L.o_Y);
   hipStream_t s = as_stream(stream);
-  if ((rc = launch_fill<unsigned long long>(D, 2 * n, 0ull, s))) return rc;
+  if (!symmetric && (rc = launch_fill<unsigned long long>(D, 2 * n, 0ull, s))) return rc;
   const int64_t nbk = ceil_div(nnz, 256);
   const int nb = int(nbk < UMAP_RED_BLOCKS ? nbk : UMAP_RED_BLOCKS);
   hipLaunchKernelGGL(umap_wmax_kernel, dim3(unsigned(nb)), dim3(256), 0, s, val, nnz, part);
@@ -318,12 +383,27 @@ extern "C" int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, con
   TSNE_CHECK_LAUNCH();
   const dim3 grid(unsigned(ceil_div(n, 256)));
   float2* Y2 = reinterpret_cast<float2*>(Y);
+  float2* cur = Y2;
+  float2* nxt = Yb;
   for (int t = epoch_begin; t < epoch_end; ++t) {
     const float alpha = float(alpha0 * (1.0 - double(t) / double(n_epochs)));
-    hipLaunchKernelGGL(umap_epoch_kernel, grid, dim3(256), 0, s, Y2, n, row_ptr, col, val, nnz, wmax, float(a),
-                       float(b), alpha, int(neg_rate), seed, int(t), D);
-    TSNE_CHECK_LAUNCH();
-    hipLaunchKernelGGL(umap_apply_kernel, grid, dim3(256), 0, s, Y2, n, D);
+    if (symmetric) {
+      hipLaunchKernelGGL(umap_epoch_sym_kernel, grid, dim3(256), 0, s, cur, nxt, n, row_ptr, col, val, nnz, wmax,
+                         float(a), float(b), alpha, int(neg_rate), seed, int(t));
+      TSNE_CHECK_LAUNCH();
+      float2* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+    } else {
+      hipLaunchKernelGGL(umap_epoch_kernel, grid, dim3(256), 0, s, Y2, n, row_ptr, col, val, nnz, wmax, float(a),
+                         float(b), alpha, int(neg_rate), seed, int(t), D);
+      TSNE_CHECK_LAUNCH();
+      hipLaunchKernelGGL(umap_apply_kernel, grid, dim3(256), 0, s, Y2, n, D);
+      TSNE_CHECK_LAUNCH();
+    }
+  }
+  if (cur != Y2) {
+    hipLaunchKernelGGL(umap_copy_kernel, grid, dim3(256), 0, s, cur, Y2, n);
     TSNE_CHECK_LAUNCH();
   }
   return TSNE_OK;

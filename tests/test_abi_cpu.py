@@ -161,12 +161,13 @@ def test_umap_arguments_and_workspace(L):
     assert ws_query(fu, fake, fake, 100, 100, fake, fake, fake, NULL, fake)[0] == IA
     lay = L.tsne_umap_layout
 
-    def lq(Y=fake, n=1000, nnz=20000, a=1.5, b=0.9, alpha=1.0, neg=5, ne=200, t0=0, t1=200):
-        return ws_query(lay, Y, n, fake, fake, fake, nnz, C.c_double(a), C.c_double(b), C.c_double(alpha), neg, ne,
-                        t0, t1, C.c_uint64(7))
+    def lq(Y=fake, n=1000, nnz=20000, sym=1, a=1.5, b=0.9, alpha=1.0, neg=5, ne=200, t0=0, t1=200):
+        return ws_query(lay, Y, n, fake, fake, fake, nnz, sym, C.c_double(a), C.c_double(b), C.c_double(alpha), neg,
+                        ne, t0, t1, C.c_uint64(7))
 
     rc, need = lq()
-    assert rc == 0 and 16 * 1000 <= need <= 16 * 1000 + 4096
+    assert rc == 0 and 24 * 1000 <= need <= 24 * 1000 + 4096
+    assert lq(sym=0)[0] == 0 and lq(sym=2)[0] == IA
     assert lq(Y=NULL)[0] == IA and lq(n=1)[0] == IA and lq(nnz=0)[0] == IA
     assert lq(a=0.0)[0] == IA and lq(b=-1.0)[0] == IA and lq(alpha=-0.1)[0] == IA
     assert lq(neg=-1)[0] == IA and lq(neg=65)[0] == IA and lq(ne=0)[0] == IA

@@ -105,6 +105,28 @@ def test_umap_epochs_match_oracle(dev, t0, t1, neg):
     e = np.abs(Yg.cpu().numpy() - Yo).max()
     tol = step_tol(Y0, Yo) * (t1 - t0)
     assert e <= tol, (e, tol)
+    # the scattering path gives the same bits on this symmetric graph
+    Ys = api.umap_layout(to_dev(Y0, dev), G, a, b, n_epochs, 1.0, neg, seed=123, epochs=(t0, t1), symmetric=False)
+    assert torch.equal(Ys, Yg)
+
+
+def test_umap_epochs_directed_graph(dev):
+    # a graph that is not symmetric (the directed kNN lists themselves):
+    # only the scattering path applies; each entry moves both of its ends
+    say("umap epochs, directed graph")
+    n, k, n_epochs = 3000, 10, 100
+    idx, _ = synth.random_knn_graph(n, k, 13)
+    order = np.argsort(idx, axis=1, kind="stable")
+    col = np.take_along_axis(idx, order, 1).ravel().astype(np.int32)
+    valf = np.take_along_axis(np.random.default_rng(13).random((n, k)).astype(np.float32), order, 1).ravel()
+    rp = np.arange(0, n * k + 1, k, dtype=np.int64)
+    G = api.SparseP(to_dev(rp, dev), to_dev(col, dev), to_dev(valf, dev), None, n)
+    Y0 = synth.umap_init(n, 14)
+    a, b = 1.2, 0.95
+    Yg = api.umap_layout(to_dev(Y0, dev), G, a, b, n_epochs, 0.5, 5, seed=15, epochs=(30, 32), symmetric=False)
+    Yo = U.layout(Y0.astype(np.float64), rp, col, valf, n_epochs, a, b, 0.5, 5, 15, epochs=(30, 32))
+    e = np.abs(Yg.cpu().numpy() - Yo).max()
+    assert e <= 2 * step_tol(Y0, Yo), (e, step_tol(Y0, Yo))
 
 
 def test_umap_layout_deterministic(dev):
@@ -157,3 +179,5 @@ def test_umap_union_and_epoch_full_size(dev):
     Yo = U.layout_epoch(Y0.astype(np.float64), rp, col, valf, 150, 200, 0.583, 1.334, 1.0, 5, 5)
     e = np.abs(Yg.cpu().numpy() - Yo).max()
     assert e <= step_tol(Y0, Yo), (e, step_tol(Y0, Yo))
+    Ys = api.umap_layout(to_dev(Y0, dev), G, 0.583, 1.334, 200, 1.0, 5, seed=5, epochs=(150, 151), symmetric=False)
+    assert torch.equal(Ys, Yg)
