@@ -11,8 +11,9 @@ dominant kernel's average per-launch time for the roofline.  Outside the timed r
 comparison, and the CPU-baseline leg (the FP64 oracle timed on a bounded
 sample of the same workload, which also yields the error statistics), the
 KL autograd timing, the interpolated (FFT) gradient timed against the
-exact one at the C5 point count, and the PCA that produces the embedding's
-input (200k cells x 2000 genes, 50 components, 2 power iterations).
+exact one at the C5 point count, the PCA that produces the embedding's
+input (200k cells x 2000 genes, 50 components, 2 power iterations), and
+UMAP on the C5 points (k = 15 neighbour graph, fuzzy union, 200 epochs).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 """
@@ -50,6 +51,8 @@ def parse():
     ap.add_argument("--pca-n", type=int, default=200_000,
                     help="cells of the PCA timing (tsne_pca, k = 50 of 64, q = 2; 0: skip)")
     ap.add_argument("--pca-g", type=int, default=2000, help="genes of the PCA timing")
+    ap.add_argument("--umap-n", type=int, default=1_000_000,
+                    help="points of the UMAP timing (c5 shape, k = 15, 200 epochs; 0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -335,6 +338,53 @@ def main():
         del Xp, Om, sc, comp, sv, mu, wsp
         progress(f"pca at {npc} x {gpc} done")
 
+    # --- UMAP on the c5 points: kNN (k = 15), weights, union, layout -------
+    umap = {}
+    if args.umap_n:
+        nu, ku, n_ep, neg = args.umap_n, 15, 200, 5
+        Xu, labu = synth.make_points("c5", n=nu)
+        Xu = torch.from_numpy(Xu).to(dev)
+        wsu = api.Workspace()
+        a_u, b_u = api.umap_fit_ab(0.5)
+        runs = []
+        for rep in range(2):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record(stream)
+            idu, d2u = api.knn(Xu, ku, "bf16", n_cand=2 * ku, ws=wsu)
+            ev[1].record(stream)
+            _, _, wu = api.umap_weights(d2u)
+            ev[2].record(stream)
+            Gu = api.umap_fuzzy_union(idu, wu, ws=wsu)  # reads nnz back (one sync)
+            ev[3].record(stream)
+            Yu = torch.from_numpy(synth.umap_init(nu, 3)).to(dev)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            api.umap_layout(Yu, Gu, a_u, b_u, n_ep, 1.0, neg, seed=1, ws=wsu)
+            ev[4].record(stream)
+            torch.cuda.synchronize()
+            runs.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]),
+                         t0.elapsed_time(ev[4])))
+        kn, wt, un, lay = (float(np.median([r[q] for r in runs])) for q in range(4))
+        r_u = Gu.val / Gu.val.max()
+        sampled = float(torch.floor(float(n_ep) * r_u).sum().item())  # entries sampled over all epochs
+        inter = sampled * (1 + neg)
+        # structure check without the oracle: 10-NN label purity in the
+        # embedding on 2000 sampled points
+        rows = torch.from_numpy(np.random.default_rng(12).choice(nu, 2000, replace=False)).to(dev)
+        dd = torch.cdist(Yu[rows].double(), Yu.double())
+        dd[torch.arange(2000, device=dev), rows] = float("inf")
+        nn10 = torch.topk(dd, 10, largest=False).indices.cpu().numpy()
+        lab_t = labu[rows.cpu().numpy()]
+        purity = float((labu[nn10] == lab_t[:, None]).mean())
+        umap = {"n": nu, "k": ku, "knn": "bf16 + fp32 re-rank of 2k", "nnz": int(Gu.nnz), "n_epochs": n_ep,
+                "neg_rate": neg, "min_dist": 0.5, "a": a_u, "b": b_u, "init": "uniform [-10, 10]^2, seed 3",
+                "knn_ms": kn, "weights_ms": wt, "union_ms": un, "layout_ms": lay, "ms_per_epoch": lay / n_ep,
+                "total_ms": kn + wt + un + lay, "sampled_entries": sampled,
+                "pair_interactions_per_s": inter / (lay * 1e-3), "label_purity_10nn_sample": purity}
+        del Xu, idu, d2u, wu, Gu, Yu, wsu, dd
+        progress(f"umap at {nu} done")
+
     # --- CPU baseline: the FP64 oracle on a bounded sample ------------------
     cpu = None
     errors = {}
@@ -439,6 +489,7 @@ def main():
         "kl_autograd": diff,
         "interpolated_gradient": interp,
         "pca": pca,
+        "umap": umap,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "errors_vs_fp64": errors,
