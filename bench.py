@@ -14,6 +14,8 @@ KL autograd timing, the interpolated (FFT) gradient timed against the
 exact one at the C5 point count, the PCA that produces the embedding's
 input (200k cells x 2000 genes, 50 components, 2 power iterations), and
 UMAP on the C5 points (k = 15 neighbour graph, fuzzy union, 200 epochs).
+Those legs run under the resource monitor (0.1 s samples), whose per-leg
+summary (GPU activity, VRAM, power, CPU) is the record's `telemetry`.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 """
@@ -54,6 +56,8 @@ def parse():
     ap.add_argument("--umap-n", type=int, default=1_000_000,
                     help="points of the UMAP timing (c5 shape, k = 15, 200 epochs; 0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-monitor", action="store_true",
+                    help="skip the telemetry (GPU activity, VRAM, power per leg) of the legs after the timed region")
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="launch one device copy of this many MiB first (reference for HBM byte counters)")
@@ -185,7 +189,19 @@ def main():
     digest = source_digest(KLGRAD_SOURCES)
     traffic = traffic_from_profile(digest, args.workload)
 
+    # --- telemetry of the legs below (outside the timed region) -----------
+    mon = None
+    if not args.no_monitor:
+        from paper_2605_13928_amd import monitor as _monitor
+
+        mon = _monitor.Monitor(period=0.1, device=dev.index or 0)  # CSV files in a fresh temporary directory
+
+    def phase(name):
+        if mon is not None:
+            mon.timestamp(name)
+
     # --- BF16-MFMA vs FP32 kNN build, outside the timed region -------------
+    phase("knn_compare")
     knn_cmp = {}
     ncmp = args.knn_compare_n
     if ncmp:
@@ -239,6 +255,7 @@ def main():
         del Xc, i32, d32, i16, d16, P32, P16, diff, both, rel
         progress(f"kNN comparison at n={ncmp} done")
 
+    phase("autograd")
     # --- differentiation form (KL autograd) at the 50k-point shape ----------
     diff = {}
     if args.autograd_n:
@@ -290,6 +307,7 @@ def main():
         return float(np.median(ts)), out
 
     # --- interpolated repulsion (tsne_kl_grad_fft) against the exact pass ---
+    phase("interpolated_gradient")
     interp = {}
     if args.fft_n:
         wf = synth.WORKLOADS["c5"]
@@ -313,6 +331,7 @@ def main():
         progress(f"interpolated gradient at n={nf} done")
 
     # --- PCA (tsne_pca): randomized truncated SVD of a cells x genes matrix ---
+    phase("pca")
     pca = {}
     if args.pca_n:
         npc, gpc, kpc, qpc = args.pca_n, args.pca_g, 50, 2
@@ -339,6 +358,7 @@ def main():
         progress(f"pca at {npc} x {gpc} done")
 
     # --- UMAP on the c5 points: kNN (k = 15), weights, union, layout -------
+    phase("umap")
     umap = {}
     if args.umap_n:
         nu, ku, n_ep, neg = args.umap_n, 15, 200, 5
@@ -385,6 +405,7 @@ def main():
         del Xu, idu, d2u, wu, Gu, Yu, wsu, dd
         progress(f"umap at {nu} done")
 
+    phase("cpu_baseline")
     # --- CPU baseline: the FP64 oracle on a bounded sample ------------------
     cpu = None
     errors = {}
@@ -460,6 +481,16 @@ def main():
             errors[f"Z_rel_ystd{ystd:g}"] = abs(Zg.item() - Zo) / Zo
             errors[f"KL_rel_ystd{ystd:g}"] = abs(klg.item() - klo) / abs(klo)
 
+    telemetry = None
+    if mon is not None:
+        ses = mon.stop()
+        keep = ("duration_s", "samples", "mean_gfx_pct", "max_gfx_pct", "max_hip_used_bytes", "mean_power_w",
+                "max_power_w", "max_temp_hotspot_c", "mean_proc_cpu_pct", "max_proc_rss_bytes")
+        telemetry = {"period_s": 0.1, "gpu_sampled": bool(np.isfinite(ses.data["gfx_pct"]).any()),
+                     "sample_us_median": float(np.median(ses.data["sample_us"])) if ses.t.size else None,
+                     "steps": {r["name"]: {k: (None if isinstance(r[k], float) and not np.isfinite(r[k]) else r[k])
+                                           for k in keep} for r in ses.steps if r["name"] != "start"}}
+
     roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
                 "kernel": "rep_sym_kernel (all-pairs Student-t repulsion and Z of tsne_kl_grad)",
@@ -492,6 +523,7 @@ def main():
         "umap": umap,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "telemetry": telemetry,
         "errors_vs_fp64": errors,
     }
     print(json.dumps(rec), flush=True)

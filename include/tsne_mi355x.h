@@ -404,6 +404,52 @@ int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, const int32_t*
                      int32_t epoch_begin, int32_t epoch_end, uint64_t seed, void* workspace, size_t* workspace_bytes,
                      void* stream);
 
+/*
+ * Resource monitor of a workload (the analogue of the paper's GPU monitor,
+ * Section 2, and of its CPU monitor of the workload's process, Section 3.2).
+ * Host-only calls, no device work.
+ *
+ * tsne_monitor_start -- starts a sampler thread.  Every period_s seconds
+ * (on a fixed grid from the start) it appends to samples_csv one row of
+ *   t_s, gfx_pct, umc_pct, vram_used_bytes, vram_total_bytes, temp_edge_c,
+ *   temp_hotspot_c, temp_vram_c, power_w, proc_cpu_pct, proc_rss_bytes,
+ *   hip_used_bytes, sample_us
+ * (seconds since start, taken after the row's last reading; graphics /
+ * memory-controller activity, VRAM and temperatures and socket power of
+ * HIP device hip_device from amd-smi;
+ * CPU share over the last period and resident bytes of process pid from
+ * /proc, pid 0 = the calling process; device memory in use as the HIP
+ * runtime reports it, total - free; the time one sample took).  The
+ * activity and power readings are the device's own running averages and
+ * trail a change of load by a fraction of a second.  GPU
+ * columns are nan when amd-smi, the device (hip_device < 0 for none) or a
+ * sensor is unavailable.  events_csv receives (t_s, name) rows: "start" at 0,
+ * the timestamps, "stop" at the end.  Both files are created (truncated)
+ * and flushed row by row.
+ *   period_s in [1e-3, 3600]; pid >= 0; *out receives the handle.
+ *   Errors: TSNE_ERR_INVALID_ARG (bad argument, a file cannot be opened).
+ * tsne_monitor_timestamp -- appends (now, name) to the events; commas,
+ *   quotes and line breaks in name become '_'.  Thread-safe.
+ * tsne_monitor_has_gpu -- 1 when the GPU columns are being sampled.
+ * tsne_monitor_stop -- takes a last sample, writes "stop", closes the files
+ *   and frees the handle.
+ * tsne_monitor_steps -- the step table: step k < n_events - 1 is the
+ *   interval [events[k], events[k + 1]) (each interval assigned to the first
+ *   of its two timestamps, as the paper's workflow figure does); over the
+ *   samples t[i] in it, count[k], and per field q the mean and maximum of
+ *   the finite values[i][q] (nan when none): mean, maxv [n_events - 1][n_fields].
+ *   t ascending [n], values [n][n_fields] (host arrays), events ascending
+ *   (n_events >= 2).
+ */
+typedef struct tsne_monitor tsne_monitor;
+int tsne_monitor_start(double period_s, int32_t hip_device, int32_t pid, const char* samples_csv,
+                       const char* events_csv, tsne_monitor** out);
+int tsne_monitor_timestamp(tsne_monitor* monitor, const char* name);
+int tsne_monitor_has_gpu(const tsne_monitor* monitor);
+int tsne_monitor_stop(tsne_monitor* monitor);
+int tsne_monitor_steps(const double* t, const double* values, int64_t n, int32_t n_fields, const double* events,
+                       int64_t n_events, int64_t* count, double* mean, double* maxv);
+
 #ifdef __cplusplus
 }
 #endif

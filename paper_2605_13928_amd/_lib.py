@@ -59,6 +59,11 @@ SIGNATURES = {
     "tsne_umap_fuzzy_union": (C.c_int, [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_umap_layout": (C.c_int, [_p, _i64, _p, _p, _p, _i64, _i32, C.c_double, C.c_double, C.c_double, _i32, _i32,
                                    _i32, _i32, C.c_uint64, _p, _szp, _p]),
+    "tsne_monitor_start": (C.c_int, [C.c_double, _i32, _i32, C.c_char_p, C.c_char_p, C.POINTER(C.c_void_p)]),
+    "tsne_monitor_timestamp": (C.c_int, [_p, C.c_char_p]),
+    "tsne_monitor_has_gpu": (C.c_int, [_p]),
+    "tsne_monitor_stop": (C.c_int, [_p]),
+    "tsne_monitor_steps": (C.c_int, [_p, _p, _i64, _i32, _p, _i64, _p, _p, _p]),
 }
 
 _lib = None
