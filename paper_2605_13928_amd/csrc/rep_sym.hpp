@@ -377,7 +377,12 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       }
     }
 
-    for (int us = w; us < nsub; us += SYM_WAVES) {
+    // subblocks past the last point are skipped: a padded point sits at
+    // 1e30, so every pair with it has weight exactly 0 and adds exact zeros
+    // (the result is the same bits as with them)
+    const int ni_end = int(min(int64_t(nsub), (n - s * S + 63) / 64));
+    const int nj_end = int(min(int64_t(nsub), (n - t * S + 63) / 64));
+    for (int us = w; us < ni_end; us += SYM_WAVES) {
       // this wave's i-subblock us: points s S + 64 us + 8a + r
       float xi[8], yi[8];
 #pragma unroll
@@ -398,7 +403,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       int since_fold = 0;
       const int comp = lane >> 5;
       const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
-      for (int v = v0; v < nsub; ++v) {
+      for (int v = v0; v < nj_end; ++v) {
         float4 jc[4];
         {
           const float4* p = reinterpret_cast<const float4*>(jpts + 64 * v + 8 * b);
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
           }
         }
         // fold the i-side sums into FP64 every 8 tiles (after an 8-lane reduce)
-        if (++since_fold == 8 || v == nsub - 1) {
+        if (++since_fold == 8 || v == nj_end - 1) {
           since_fold = 0;
           float vi[16];
 #pragma unroll

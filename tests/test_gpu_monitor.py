@@ -21,6 +21,7 @@ def test_monitor_sees_workload_phases(dev, tmp_path):
     Y = to_dev(synth.random_embedding(20_000, 10.0, 4), dev)
     api.kl_grad(Y, P, 1.0)
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # so that the 8 GB below is a new device allocation, not torch's cache
     mon = monitor.Monitor(period=0.05, device=dev.index or 0, directory=str(tmp_path))
     assert mon.has_gpu
     time.sleep(0.5)
@@ -53,8 +54,8 @@ def test_monitor_sees_workload_phases(dev, tmp_path):
     assert st["alloc"]["max_hip_used_bytes"] >= st["start"]["max_hip_used_bytes"] + 7.5e9
     assert st["release"]["samples"] > 0
     assert s.data["hip_used_bytes"][-1] <= st["alloc"]["max_hip_used_bytes"] - 7.5e9
-    if np.nanmax(s.data["vram_used_bytes"]) > 0:  # amd-smi's reading, where the device reports it
-        assert st["alloc"]["max_vram_used_bytes"] >= st["start"]["max_vram_used_bytes"] + 7.5e9
+    # amd-smi's own VRAM figure is recorded too but not checked: it trails
+    # frees by seconds (it read 15 GB here while HIP reported 1.8 GB)
     # the device's activity and power are running averages that trail the
     # load by a fraction of a second: the compute phase reaches full activity
     assert st["compute"]["max_gfx_pct"] >= 50.0 and st["compute"]["mean_gfx_pct"] > st["start"]["mean_gfx_pct"]
