@@ -103,7 +103,7 @@ def progress(msg):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
 
     import numpy as np

@@ -27,7 +27,7 @@ R_i = sum_j w_ij^2 (y_i - y_j) = z_i phi2_i - phi3_i and Z = sum_i phi1_i - n
 (the j = i terms: w_ii = 1 in phi1; they cancel exactly in R).  Kernels:
 K1(d) = 1 / (1 + |d|^2), K2 = K1^2; charges 1 and z_x, z_y.
 
-Grid parameters (the reading this build takes of the method's settings):
+Grid parameters (readings of the method's settings):
 lo = min over both coordinates, range = max - lo (both in the points'
 precision), B = clamp(ceil(range / max_box_width), min_boxes, max_fft // (2 p)),
 h = range / B (in FP64; range 0 is replaced by 1e-3), box index
