@@ -181,3 +181,17 @@ def test_umap_union_and_epoch_full_size(dev):
     assert e <= step_tol(Y0, Yo), (e, step_tol(Y0, Yo))
     Ys = api.umap_layout(to_dev(Y0, dev), G, 0.583, 1.334, 200, 1.0, 5, seed=5, epochs=(150, 151), symmetric=False)
     assert torch.equal(Ys, Yg)
+
+
+def test_umap_gather_epochs_equal_scatter_large(dev):
+    # 300,000 points, six epochs: the gather path (each vertex takes its own
+    # attractive steps twice) gives the scattering path's result bit for bit
+    say("umap gather vs scatter, 300k")
+    n, k = 300_000, 15
+    idx, _ = synth.random_knn_graph(n, k, 31)
+    w = np.random.default_rng(31).random((n, k)).astype(np.float32)
+    G = gpu_union(dev, idx, w)
+    Y0 = to_dev(synth.umap_init(n, 32), dev)
+    A = api.umap_layout(Y0.clone(), G, 0.583, 1.334, 200, epochs=(0, 6), seed=3, symmetric=True)
+    B = api.umap_layout(Y0.clone(), G, 0.583, 1.334, 200, epochs=(0, 6), seed=3, symmetric=False)
+    assert torch.equal(A, B) and not torch.equal(A, Y0)
