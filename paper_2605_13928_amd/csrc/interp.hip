@@ -160,12 +160,43 @@ __device__ __forceinline__ int fi_box(float y, const FiParams& g) {
   return int(fmin(fmax(floor(t), 0.0), double(g.B - 1)));
 }
 
+// ctr[key] += 1 for every active lane, returning the lane's slot (the old
+// count plus its rank among the lanes counted with it).  Lanes that share
+// a key are counted together: for the (at most four) keys of the lowest
+// pending lanes, one atomic per key; the rest one atomic per lane.  When
+// most points fall in a few boxes this removes nearly all the contended
+// atomics; with spread points it costs a few ballots.
+__device__ __forceinline__ int fi_wave_inc(int* __restrict__ ctr, int key, bool active) {
+  const int lane = lane_id();
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  uint64_t pending = __ballot(active);
+  int slot = 0;
+  for (int it = 0; it < 4 && pending; ++it) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int k = __shfl(key, leader);
+    const uint64_t mask = __ballot(active && key == k) & pending;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[k], __popcll(mask));
+    base = __shfl(base, leader);
+    if ((mask >> lane) & 1) slot = base + __popcll(mask & below);
+    pending &= ~mask;
+  }
+  if ((pending >> lane) & 1) slot = atomicAdd(&ctr[key], 1);
+  return slot;
+}
+
 __global__ __launch_bounds__(256) void fi_count_kernel(const float2* __restrict__ Y, int64_t n,
                                                        const FiParams* __restrict__ gp, int* __restrict__ cnt) {
   const FiParams g = *gp;
-  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * 256) {
-    const float2 y = Y[i];
-    atomicAdd(&cnt[fi_box(y.x, g) * g.B + fi_box(y.y, g)], 1);
+  for (int64_t base = int64_t(blockIdx.x) * 256; base < n; base += int64_t(gridDim.x) * 256) {
+    const int64_t i = base + threadIdx.x;
+    const bool act = i < n;
+    int b = 0;
+    if (act) {
+      const float2 y = Y[i];
+      b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
+    }
+    fi_wave_inc(cnt, b, act);
   }
 }
 
@@ -174,15 +205,53 @@ __global__ __launch_bounds__(256) void fi_scatter_kernel(const float2* __restric
                                                          const int64_t* __restrict__ off, int* __restrict__ cur,
                                                          int32_t* __restrict__ order) {
   const FiParams g = *gp;
-  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * 256) {
-    const float2 y = Y[i];
-    const int b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
-    order[off[b] + atomicAdd(&cur[b], 1)] = int32_t(i);
+  for (int64_t base = int64_t(blockIdx.x) * 256; base < n; base += int64_t(gridDim.x) * 256) {
+    const int64_t i = base + threadIdx.x;
+    const bool act = i < n;
+    int b = 0;
+    if (act) {
+      const float2 y = Y[i];
+      b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
+    }
+    const int slot = fi_wave_inc(cur, b, act);
+    if (act) order[off[b] + slot] = int32_t(i);
+  }
+}
+
+// Points per thread of the node sums.  A box holding more (a compact or
+// clustered embedding can put most points in a few boxes) is split into
+// chunks of this many points, one thread each, so no thread walks a long
+// box alone.
+constexpr int FI_HEAVY = 64;
+
+// Adds the charges 1, z_x, z_y of the sorted points [e0, e1) (one box)
+// times the tensor Lagrange weights to acc, in fixed point.
+template <int P>
+__device__ __forceinline__ void fi_accum_range(const float2* __restrict__ Y, const FiParams& g,
+                                               const int32_t* __restrict__ order, int64_t e0, int64_t e1,
+                                               long long (&acc)[3][P][P]) {
+  for (int64_t e = e0; e < e1; ++e) {
+    const float2 y = Y[order[e]];
+    double Lx[P], Ly[P];
+    fi_weights<P>(y.x, g, Lx);
+    fi_weights<P>(y.y, g, Ly);
+    const double zx = double(y.x) - g.c, zy = double(y.y) - g.c;
+#pragma unroll
+    for (int kx = 0; kx < P; ++kx) {
+#pragma unroll
+      for (int ky = 0; ky < P; ++ky) {
+        const double w = Lx[kx] * Ly[ky] * g.scale;
+        acc[0][kx][ky] += __double2ll_rn(w);
+        acc[1][kx][ky] += __double2ll_rn(w * zx);
+        acc[2][kx][ky] += __double2ll_rn(w * zy);
+      }
+    }
   }
 }
 
 // Node sums of box b (thread b < B^2): channel c at G + c N^2, node
-// (gx, gy) at gx N + gy.
+// (gx, gy) at gx N + gy.  A box of more than FI_HEAVY points gets zeros
+// here; its chunks are added by fi_accum_heavy_kernel.
 template <int P>
 __global__ __launch_bounds__(256) void fi_accum_kernel(const float2* __restrict__ Y,
                                                        const FiParams* __restrict__ gp,
@@ -200,23 +269,8 @@ __global__ __launch_bounds__(256) void fi_accum_kernel(const float2* __restrict_
       for (int kx = 0; kx < P; ++kx)
 #pragma unroll
         for (int ky = 0; ky < P; ++ky) acc[c][kx][ky] = 0;
-    for (int64_t e = off[b]; e < off[b + 1]; ++e) {
-      const float2 y = Y[order[e]];
-      double Lx[P], Ly[P];
-      fi_weights<P>(y.x, g, Lx);
-      fi_weights<P>(y.y, g, Ly);
-      const double zx = double(y.x) - g.c, zy = double(y.y) - g.c;
-#pragma unroll
-      for (int kx = 0; kx < P; ++kx) {
-#pragma unroll
-        for (int ky = 0; ky < P; ++ky) {
-          const double w = Lx[kx] * Ly[ky] * g.scale;
-          acc[0][kx][ky] += __double2ll_rn(w);
-          acc[1][kx][ky] += __double2ll_rn(w * zx);
-          acc[2][kx][ky] += __double2ll_rn(w * zy);
-        }
-      }
-    }
+    const int64_t e0 = off[b], e1 = off[b + 1];
+    if (e1 - e0 <= FI_HEAVY) fi_accum_range<P>(Y, g, order, e0, e1, acc);
     const int bx = int(b / g.B), by = int(b % g.B);
 #pragma unroll
     for (int kx = 0; kx < P; ++kx) {
@@ -225,6 +279,89 @@ __global__ __launch_bounds__(256) void fi_accum_kernel(const float2* __restrict_
         const int64_t node = int64_t(P * bx + kx) * g.N + (P * by + ky);
 #pragma unroll
         for (int c = 0; c < 3; ++c) G[c * NN + node] = (unsigned long long)acc[c][kx][ky];
+      }
+    }
+  }
+}
+
+// nch[b] = FI_HEAVY-point chunks of box b when it holds more than FI_HEAVY
+// points, else 0 (b < nbox, the workspace's box count).
+__global__ __launch_bounds__(256) void fi_chunks_kernel(const FiParams* __restrict__ gp,
+                                                        const int* __restrict__ cnt, int64_t nbox,
+                                                        int* __restrict__ nch) {
+  const FiParams g = *gp;
+  const int64_t nb = int64_t(g.B) * g.B;
+  for (int64_t b = gtid(); b < nbox; b += int64_t(gridDim.x) * 256)
+    nch[b] = (b < nb && cnt[b] > FI_HEAVY) ? (cnt[b] + FI_HEAVY - 1) / FI_HEAVY : 0;
+}
+
+// The chunks of the heavy boxes, one thread each: chunk c belongs to the box
+// b with choff[b] <= c < choff[b + 1] (binary search) and covers its sorted
+// points off[b] + FI_HEAVY (c - choff[b]) onwards.  Chunks of one box are
+// consecutive, so a wave's chunks usually share a box: then its sums are
+// added across the wave (integer shuffles, exact) and one lane adds them
+// to the box's nodes; otherwise every lane adds its own.  The nodes were
+// zeroed by fi_accum_kernel; the integer sums are exact in any order.
+template <int P>
+__global__ __launch_bounds__(256) void fi_accum_heavy_kernel(const float2* __restrict__ Y,
+                                                             const FiParams* __restrict__ gp,
+                                                             const int64_t* __restrict__ off,
+                                                             const int32_t* __restrict__ order,
+                                                             const int64_t* __restrict__ choff, int64_t nbox,
+                                                             unsigned long long* __restrict__ G) {
+  const FiParams g = *gp;
+  const int64_t H = choff[nbox];
+  const int64_t NN = int64_t(g.N) * g.N;
+  for (int64_t base = int64_t(blockIdx.x) * 256; base < H; base += int64_t(gridDim.x) * 256) {
+    const int64_t c = base + threadIdx.x;
+    const bool act = c < H;
+    int64_t b = -1;
+    long long acc[3][P][P];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int kx = 0; kx < P; ++kx)
+#pragma unroll
+        for (int ky = 0; ky < P; ++ky) acc[q][kx][ky] = 0;
+    if (act) {
+      int64_t lo = 0, hi = nbox;  // last b with choff[b] <= c
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (choff[mid] <= c) lo = mid;
+        else hi = mid;
+      }
+      b = lo;
+      const int64_t e0 = off[b] + FI_HEAVY * (c - choff[b]);
+      const int64_t e1 = e0 + FI_HEAVY < off[b + 1] ? e0 + FI_HEAVY : off[b + 1];
+      fi_accum_range<P>(Y, g, order, e0, e1, acc);
+    }
+    // one box across the wave's active lanes?
+    int64_t bmin = act ? b : INT64_MAX, bmax = act ? b : -1;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      const int64_t o1 = int64_t(shfl_xor_u64(uint64_t(bmin), m)), o2 = int64_t(shfl_xor_u64(uint64_t(bmax), m));
+      bmin = o1 < bmin ? o1 : bmin;
+      bmax = o2 > bmax ? o2 : bmax;
+    }
+    const bool one = bmin == bmax;
+    const int64_t bb = one ? bmin : b;
+    const int bx = int(bb / g.B), by = int(bb % g.B);
+#pragma unroll
+    for (int kx = 0; kx < P; ++kx) {
+#pragma unroll
+      for (int ky = 0; ky < P; ++ky) {
+        const int64_t node = int64_t(P * bx + kx) * g.N + (P * by + ky);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          uint64_t v = uint64_t(acc[q][kx][ky]);
+          if (one) {
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) v += shfl_xor_u64(v, m);
+            if (lane_id() == 0) atomicAdd(&G[q * NN + node], (unsigned long long)v);
+          } else if (act) {
+            atomicAdd(&G[q * NN + node], (unsigned long long)v);
+          }
+        }
       }
     }
   }
@@ -385,7 +522,7 @@ __global__ __launch_bounds__(256) void fi_gather_kernel(const float2* __restrict
 }
 
 struct FiPlan {
-  size_t o_part, o_par, o_G, o_C, o_R, o_Zb, o_kl, o_cnt, o_cur, o_off, o_bsum, o_ord, bytes;
+  size_t o_part, o_par, o_G, o_C, o_R, o_Zb, o_kl, o_cnt, o_cur, o_off, o_bsum, o_ord, o_nch, o_choff, bytes;
   int64_t plane, nbox;  // nbox: boxes of the largest grid (B <= max_fft / 4)
 };
 
@@ -403,6 +540,8 @@ FiPlan fi_plan(int64_t n, int max_fft) {
   L.o_off = c.take(sizeof(int64_t) * size_t(L.nbox + 1));
   L.o_bsum = c.take(sizeof(int64_t) * (size_t(ceil_div(L.nbox + 1, SCAN_CHUNK)) + 1));
   L.o_ord = c.take(sizeof(int32_t) * size_t(n));
+  L.o_nch = c.take(sizeof(int) * size_t(L.nbox));
+  L.o_choff = c.take(sizeof(int64_t) * size_t(L.nbox + 1));
   L.o_G = c.take(sizeof(unsigned long long) * 3 * size_t(Nmax) * size_t(Nmax));
   L.o_C = c.take(sizeof(double2) * 3 * size_t(L.plane));
   L.o_R = c.take(sizeof(float2) * size_t(n));
@@ -414,11 +553,16 @@ FiPlan fi_plan(int64_t n, int max_fft) {
 
 template <int P>
 int fi_launch_points(bool spread, const float2* Y, int64_t n, const FiParams* par, const int64_t* off,
-                     const int32_t* order, int64_t nbox, unsigned long long* G, const double2* Cg, int64_t plane,
-                     float2* R, double* Zb, hipStream_t s) {
+                     const int32_t* order, const int64_t* choff, int64_t nbox, unsigned long long* G,
+                     const double2* Cg, int64_t plane, float2* R, double* Zb, hipStream_t s) {
   if (spread) {
     hipLaunchKernelGGL(fi_accum_kernel<P>, dim3(unsigned(ceil_div(nbox, 256))), dim3(256), 0, s, Y, par, off, order,
                        G);
+    TSNE_CHECK_LAUNCH();
+    // at most n / FI_HEAVY + (heavy boxes <= n / FI_HEAVY) chunks
+    const int64_t blocks = ceil_div(2 * ceil_div(n, FI_HEAVY), 256);
+    hipLaunchKernelGGL(fi_accum_heavy_kernel<P>, dim3(unsigned(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, Y,
+                       par, off, order, choff, nbox, G);
   } else {
     hipLaunchKernelGGL(fi_gather_kernel<P>, dim3(FI_GRID), dim3(256), 0, s, Y, n, par, Cg, plane, R, Zb);
   }
@@ -427,13 +571,14 @@ int fi_launch_points(bool spread, const float2* Y, int64_t n, const FiParams* pa
 }
 
 int fi_points(int p, bool spread, const float2* Y, int64_t n, const FiParams* par, const int64_t* off,
-              const int32_t* order, int64_t nbox, unsigned long long* G, const double2* Cg, int64_t plane, float2* R,
+              const int32_t* order, const int64_t* choff, int64_t nbox, unsigned long long* G, const double2* Cg,
+              int64_t plane, float2* R,
               double* Zb, hipStream_t s) {
   switch (p) {
-    case 2: return fi_launch_points<2>(spread, Y, n, par, off, order, nbox, G, Cg, plane, R, Zb, s);
-    case 3: return fi_launch_points<3>(spread, Y, n, par, off, order, nbox, G, Cg, plane, R, Zb, s);
-    case 4: return fi_launch_points<4>(spread, Y, n, par, off, order, nbox, G, Cg, plane, R, Zb, s);
-    default: return fi_launch_points<5>(spread, Y, n, par, off, order, nbox, G, Cg, plane, R, Zb, s);
+    case 2: return fi_launch_points<2>(spread, Y, n, par, off, order, choff, nbox, G, Cg, plane, R, Zb, s);
+    case 3: return fi_launch_points<3>(spread, Y, n, par, off, order, choff, nbox, G, Cg, plane, R, Zb, s);
+    case 4: return fi_launch_points<4>(spread, Y, n, par, off, order, choff, nbox, G, Cg, plane, R, Zb, s);
+    default: return fi_launch_points<5>(spread, Y, n, par, off, order, choff, nbox, G, Cg, plane, R, Zb, s);
   }
 }
 
@@ -481,6 +626,8 @@ extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_pt
   int64_t* off = reinterpret_cast<int64_t*>(ws + L.o_off);
   int64_t* bsum = reinterpret_cast<int64_t*>(ws + L.o_bsum);
   int32_t* order = reinterpret_cast<int32_t*>(ws + L.o_ord);
+  int* nch = reinterpret_cast<int*>(ws + L.o_nch);
+  int64_t* choff = reinterpret_cast<int64_t*>(ws + L.o_choff);
 
   hipLaunchKernelGGL(fi_bbox_kernel, dim3(FI_GRID), dim3(256), 0, s, Y2, n, part);
   TSNE_CHECK_LAUNCH();
@@ -496,14 +643,19 @@ extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_pt
   if ((rc = exclusive_scan<int>(cnt, L.nbox, off, bsum, s))) return rc;
   hipLaunchKernelGGL(fi_scatter_kernel, pgrid, dim3(256), 0, s, Y2, n, par, off, cur, order);
   TSNE_CHECK_LAUNCH();
-  if ((rc = fi_points(n_interp, true, Y2, n, par, off, order, L.nbox, G, Cg, L.plane, R, Zb, s))) return rc;
+  // the chunks of the heavy boxes (more than FI_HEAVY points), listed by a scan
+  const int64_t bgrid = ceil_div(L.nbox, 256) < 4096 ? ceil_div(L.nbox, 256) : 4096;
+  hipLaunchKernelGGL(fi_chunks_kernel, dim3(unsigned(bgrid)), dim3(256), 0, s, par, cnt, L.nbox, nch);
+  TSNE_CHECK_LAUNCH();
+  if ((rc = exclusive_scan<int>(nch, L.nbox, choff, bsum, s))) return rc;
+  if ((rc = fi_points(n_interp, true, Y2, n, par, off, order, choff, L.nbox, G, Cg, L.plane, R, Zb, s))) return rc;
   hipLaunchKernelGGL(fi_load_kernel, dim3(4096), dim3(256), 0, s, G, par, n_interp, Cg, L.plane);
   TSNE_CHECK_LAUNCH();
   if ((rc = fi_fft2(Cg, L.plane, 3, par, max_fft, -1.0, s))) return rc;
   hipLaunchKernelGGL(fi_mult_kernel, dim3(4096), dim3(256), 0, s, Cg, L.plane, par);
   TSNE_CHECK_LAUNCH();
   if ((rc = fi_fft2(Cg, L.plane, 2, par, max_fft, 1.0, s))) return rc;
-  if ((rc = fi_points(n_interp, false, Y2, n, par, off, order, L.nbox, G, Cg, L.plane, R, Zb, s))) return rc;
+  if ((rc = fi_points(n_interp, false, Y2, n, par, off, order, choff, L.nbox, G, Cg, L.plane, R, Zb, s))) return rc;
   return finalize_csr_launch(Y, n, row_ptr, col, val, exaggeration, reinterpret_cast<const float*>(R), Zb, FI_GRID,
                              grad, Z, kl, klp, s);
 }

@@ -124,3 +124,21 @@ def test_fft_grad_c5_full_size(dev):
     go = 4.0 * (Ao - Ro[rows] / Zo)
     e = rel(g[rows], go)
     assert e <= GRAD_RTOL, e
+
+
+def test_fft_grad_clustered_embedding(dev):
+    # 95% of 200,000 points in one tight cluster, the rest spread: most
+    # points share a few boxes, whose node sums are split into chunks
+    say("fft grad clustered")
+    n = 200_000
+    _, _, _, S = random_graph_P(n, 30, 10.0, 17)
+    So = widen(S)
+    rng = np.random.default_rng(18)
+    Y = np.where(rng.random((n, 1)) < 0.95, rng.normal(0.0, 0.01, (n, 2)), rng.normal(0.0, 20.0, (n, 2)))
+    Y = Y.astype(np.float32)
+    g, Z, kl = gpu_fft(dev, Y, So, 1.0)
+    go, Zo, klo = I.kl_grad(Y, So, 1.0)
+    assert rel(g, go) <= GRAD_RTOL, rel(g, go)
+    assert abs(Z - Zo) <= 1e-9 * Zo
+    g2, Z2, _ = gpu_fft(dev, Y, So, 1.0)
+    assert np.array_equal(g, g2) and Z == Z2
