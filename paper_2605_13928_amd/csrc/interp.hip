@@ -160,61 +160,81 @@ __device__ __forceinline__ int fi_box(float y, const FiParams& g) {
   return int(fmin(fmax(floor(t), 0.0), double(g.B - 1)));
 }
 
-// ctr[key] += 1 for every active lane, returning the lane's slot (the old
-// count plus its rank among the lanes counted with it).  Lanes that share
-// a key are counted together: for the (at most four) keys of the lowest
-// pending lanes, one atomic per key; the rest one atomic per lane.  When
-// most points fall in a few boxes this removes nearly all the contended
-// atomics; with spread points it costs a few ballots.
-__device__ __forceinline__ int fi_wave_inc(int* __restrict__ ctr, int key, bool active) {
-  const int lane = lane_id();
-  const uint64_t below = (uint64_t(1) << lane) - 1;
-  uint64_t pending = __ballot(active);
-  int slot = 0;
-  for (int it = 0; it < 4 && pending; ++it) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int k = __shfl(key, leader);
-    const uint64_t mask = __ballot(active && key == k) & pending;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&ctr[k], __popcll(mask));
-    base = __shfl(base, leader);
-    if ((mask >> lane) & 1) slot = base + __popcll(mask & below);
-    pending &= ~mask;
+// Counting sort of the points by box, with the counts gathered per block:
+// a block counts its points in an LDS table (open addressing, at most
+// FI_PROBE probes; a key that finds no slot is counted in global memory
+// directly) and adds each distinct box once.  When most points fall in a
+// few boxes (a compact or clustered embedding) this replaces the
+// contended global atomics on those boxes' counters by one per block.
+constexpr int FI_TBL = 4096;      // LDS slots per block
+constexpr int FI_PROBE = 8;
+constexpr int FI_CBLOCKS = 1024;  // blocks of the counting kernels
+
+__device__ __forceinline__ int fi_tbl_find(int* tkey, int key, bool insert) {
+  const uint32_t h = uint32_t(key) * 2654435761u;
+  for (int q = 0; q < FI_PROBE; ++q) {
+    const int slot = int((h + uint32_t(q)) & (FI_TBL - 1));
+    const int prev = insert ? atomicCAS(&tkey[slot], -1, key) : tkey[slot];
+    if (prev == key || (insert && prev == -1)) return slot;
+    if (!insert && prev == -1) return -1;
   }
-  if ((pending >> lane) & 1) slot = atomicAdd(&ctr[key], 1);
-  return slot;
+  return -1;
 }
 
 __global__ __launch_bounds__(256) void fi_count_kernel(const float2* __restrict__ Y, int64_t n,
                                                        const FiParams* __restrict__ gp, int* __restrict__ cnt) {
+  __shared__ int tkey[FI_TBL], tcnt[FI_TBL];
   const FiParams g = *gp;
-  for (int64_t base = int64_t(blockIdx.x) * 256; base < n; base += int64_t(gridDim.x) * 256) {
-    const int64_t i = base + threadIdx.x;
-    const bool act = i < n;
-    int b = 0;
-    if (act) {
-      const float2 y = Y[i];
-      b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
-    }
-    fi_wave_inc(cnt, b, act);
+  for (int q = threadIdx.x; q < FI_TBL; q += 256) {
+    tkey[q] = -1;
+    tcnt[q] = 0;
   }
+  __syncthreads();
+  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * 256) {
+    const float2 y = Y[i];
+    const int b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
+    const int slot = fi_tbl_find(tkey, b, true);
+    if (slot >= 0) atomicAdd(&tcnt[slot], 1);
+    else atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < FI_TBL; q += 256)
+    if (tcnt[q]) atomicAdd(&cnt[tkey[q]], tcnt[q]);
 }
 
+// The same table, twice over the block's points: first the counts, then one
+// global reservation per box (the block's range within the box), then each
+// point's position (the range's start plus its rank).  A key without a slot
+// takes its position from the global cursor directly, in both passes alike.
 __global__ __launch_bounds__(256) void fi_scatter_kernel(const float2* __restrict__ Y, int64_t n,
                                                          const FiParams* __restrict__ gp,
                                                          const int64_t* __restrict__ off, int* __restrict__ cur,
                                                          int32_t* __restrict__ order) {
+  __shared__ int tkey[FI_TBL], tcnt[FI_TBL], tbase[FI_TBL];
   const FiParams g = *gp;
-  for (int64_t base = int64_t(blockIdx.x) * 256; base < n; base += int64_t(gridDim.x) * 256) {
-    const int64_t i = base + threadIdx.x;
-    const bool act = i < n;
-    int b = 0;
-    if (act) {
-      const float2 y = Y[i];
-      b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
-    }
-    const int slot = fi_wave_inc(cur, b, act);
-    if (act) order[off[b] + slot] = int32_t(i);
+  for (int q = threadIdx.x; q < FI_TBL; q += 256) {
+    tkey[q] = -1;
+    tcnt[q] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * 256) {
+    const float2 y = Y[i];
+    const int b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
+    const int slot = fi_tbl_find(tkey, b, true);
+    if (slot >= 0) atomicAdd(&tcnt[slot], 1);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < FI_TBL; q += 256) {
+    tbase[q] = tcnt[q] ? atomicAdd(&cur[tkey[q]], tcnt[q]) : 0;
+    tcnt[q] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * 256) {
+    const float2 y = Y[i];
+    const int b = fi_box(y.x, g) * g.B + fi_box(y.y, g);
+    const int slot = fi_tbl_find(tkey, b, false);
+    const int pos = slot >= 0 ? tbase[slot] + atomicAdd(&tcnt[slot], 1) : atomicAdd(&cur[b], 1);
+    order[off[b] + pos] = int32_t(i);
   }
 }
 
@@ -637,7 +657,7 @@ extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_pt
   // counting sort of the points by box, then the per-box node sums
   if ((rc = launch_fill<int>(cnt, L.nbox, 0, s))) return rc;
   if ((rc = launch_fill<int>(cur, L.nbox, 0, s))) return rc;
-  const dim3 pgrid(unsigned(ceil_div(n, 256) < 4096 ? ceil_div(n, 256) : 4096));
+  const dim3 pgrid(unsigned(ceil_div(n, 256) < FI_CBLOCKS ? ceil_div(n, 256) : FI_CBLOCKS));
   hipLaunchKernelGGL(fi_count_kernel, pgrid, dim3(256), 0, s, Y2, n, par, cnt);
   TSNE_CHECK_LAUNCH();
   if ((rc = exclusive_scan<int>(cnt, L.nbox, off, bsum, s))) return rc;
