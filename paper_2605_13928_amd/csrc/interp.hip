@@ -245,28 +245,44 @@ __global__ __launch_bounds__(256) void fi_scatter_kernel(const float2* __restric
 constexpr int FI_HEAVY = 64;
 
 // Adds the charges 1, z_x, z_y of the sorted points [e0, e1) (one box)
-// times the tensor Lagrange weights to acc, in fixed point.
+// times the tensor Lagrange weights to acc, in fixed point.  The point
+// indices and positions are loaded eight at a time, so the loads of a batch
+// are in flight together (the sums keep their order).
+template <int P>
+__device__ __forceinline__ void fi_accum_point(float2 y, const FiParams& g, long long (&acc)[3][P][P]) {
+  double Lx[P], Ly[P];
+  fi_weights<P>(y.x, g, Lx);
+  fi_weights<P>(y.y, g, Ly);
+  const double zx = double(y.x) - g.c, zy = double(y.y) - g.c;
+#pragma unroll
+  for (int kx = 0; kx < P; ++kx) {
+#pragma unroll
+    for (int ky = 0; ky < P; ++ky) {
+      const double w = Lx[kx] * Ly[ky] * g.scale;
+      acc[0][kx][ky] += __double2ll_rn(w);
+      acc[1][kx][ky] += __double2ll_rn(w * zx);
+      acc[2][kx][ky] += __double2ll_rn(w * zy);
+    }
+  }
+}
+
 template <int P>
 __device__ __forceinline__ void fi_accum_range(const float2* __restrict__ Y, const FiParams& g,
                                                const int32_t* __restrict__ order, int64_t e0, int64_t e1,
                                                long long (&acc)[3][P][P]) {
-  for (int64_t e = e0; e < e1; ++e) {
-    const float2 y = Y[order[e]];
-    double Lx[P], Ly[P];
-    fi_weights<P>(y.x, g, Lx);
-    fi_weights<P>(y.y, g, Ly);
-    const double zx = double(y.x) - g.c, zy = double(y.y) - g.c;
+  constexpr int BT = 8;
+  int64_t e = e0;
+  for (; e + BT <= e1; e += BT) {
+    int32_t ix[BT];
+    float2 yv[BT];
 #pragma unroll
-    for (int kx = 0; kx < P; ++kx) {
+    for (int u = 0; u < BT; ++u) ix[u] = order[e + u];
 #pragma unroll
-      for (int ky = 0; ky < P; ++ky) {
-        const double w = Lx[kx] * Ly[ky] * g.scale;
-        acc[0][kx][ky] += __double2ll_rn(w);
-        acc[1][kx][ky] += __double2ll_rn(w * zx);
-        acc[2][kx][ky] += __double2ll_rn(w * zy);
-      }
-    }
+    for (int u = 0; u < BT; ++u) yv[u] = Y[ix[u]];
+#pragma unroll
+    for (int u = 0; u < BT; ++u) fi_accum_point<P>(yv[u], g, acc);
   }
+  for (; e < e1; ++e) fi_accum_point<P>(Y[order[e]], g, acc);
 }
 
 // Node sums of box b (thread b < B^2): channel c at G + c N^2, node
