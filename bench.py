@@ -15,7 +15,10 @@ exact one at the C5 point count, the PCA that produces the embedding's
 input (200k cells x 2000 genes, 50 components, 2 power iterations), and
 UMAP on the C5 points (k = 15 neighbour graph, fuzzy union, 200 epochs).
 Those legs run under the resource monitor (0.1 s samples), whose per-leg
-summary (GPU activity, VRAM, power, CPU) is the record's `telemetry`.
+summary (GPU activity, VRAM, power, CPU) is the record's `telemetry`.  The
+CPU-baseline leg also times the FP64 oracles of the widened rows
+(interpolated repulsion, PCA, one UMAP epoch) on bounded samples of the
+same recipes, beside the GPU figures (`cpu_baseline.widened_rows`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 """
@@ -461,6 +464,50 @@ def main():
                           f"{n / qrows.size:g}); calibration + symmetrisation of a full-size seeded k={w.k} graph; "
                           f"{it_desc}; host {platform.processor() or platform.machine()}"),
                "s_per_step_extrapolated": t_total}
+        # the oracles of the widened rows beside their GPU legs (bounded
+        # samples, seeded synthetic inputs of the same recipes)
+        nxt = {}
+        if interp:
+            from oracle import interp as o_interp
+
+            Yi = synth.random_embedding(interp["n"], 30.0, 4242).astype(np.float64)
+            t0 = time.perf_counter()
+            o_interp.repulsion(Yi)
+            nxt["interpolated_repulsion"] = {
+                "oracle_s": time.perf_counter() - t0, "gpu_ms_whole_call": interp["interpolated_ms"],
+                "sample": f"oracle/interp.py repulsion and Z by the same scheme (FP64 NumPy) at the leg's full "
+                          f"{interp['n']} points; the GPU figure also holds the exact CSR attraction"}
+            del Yi
+        if pca:
+            from oracle import pca as o_pca
+
+            Xo = synth.make_expression(pca["n"], pca["g"], 2024).astype(np.float64)
+            Omo = synth.make_omega(pca["g"], 2025).astype(np.float64)
+            t0 = time.perf_counter()
+            o_pca.randomized_pca(Xo, pca["k"], Omo, pca["q"])
+            nxt["pca"] = {"oracle_s": time.perf_counter() - t0, "gpu_ms": pca["ms"],
+                          "sample": f"oracle/pca.py (FP64 NumPy) at the leg's full {pca['n']} x {pca['g']}, q = {pca['q']}"}
+            del Xo, Omo
+        if umap:
+            from oracle import umap as o_umap
+
+            nu_o = 100_000
+            io, _ = synth.random_knn_graph(nu_o, umap["k"], 21)
+            rp_o, col_o, val_o = o_umap.fuzzy_union(io, np.random.default_rng(21).random((nu_o, umap["k"])), nu_o)
+            Yo_u = synth.umap_init(nu_o, 22).astype(np.float64)
+            t0 = time.perf_counter()
+            o_umap.layout_epoch(Yo_u, rp_o, col_o, val_o.astype(np.float32), umap["n_epochs"] // 2, umap["n_epochs"],
+                                umap["a"], umap["b"], 1.0, umap["neg_rate"], 5)
+            t_ep = time.perf_counter() - t0
+            nxt["umap_epoch"] = {
+                "oracle_s": t_ep, "oracle_s_scaled_to_leg": t_ep * umap["nnz"] / col_o.size,
+                "gpu_ms_per_epoch": umap["ms_per_epoch"],
+                "sample": f"oracle/umap.py, one mid-schedule epoch (FP64 NumPy) on a seeded {nu_o}-point k = "
+                          f"{umap['k']} graph (nnz {col_o.size}), scaled by stored entries to the leg's graph "
+                          f"(nnz {umap['nnz']})"}
+        if nxt:
+            cpu["widened_rows"] = nxt
+            progress("CPU baselines of the widened rows timed")
         # errors vs FP64 from identical inputs
         g_idx = idx.cpu().numpy()[qrows]
         errors["knn_set_agreement_sampled_rows"] = float(
