@@ -432,7 +432,8 @@ int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, const int32_t*
  *   quotes and line breaks in name become '_'.  Thread-safe.
  * tsne_monitor_has_gpu -- 1 when the GPU columns are being sampled.
  * tsne_monitor_stop -- takes a last sample, writes "stop", closes the files
- *   and frees the handle.
+ *   and frees the handle; the handle must not be used afterwards (and no
+ *   timestamp may race with the stop).
  * tsne_monitor_steps -- the step table: step k < n_events - 1 is the
  *   interval [events[k], events[k + 1]) (each interval assigned to the first
  *   of its two timestamps, as the paper's workflow figure does); over the
