@@ -89,3 +89,22 @@ def test_pca_cells_full_size(dev):
     rows = np.random.default_rng(1).choice(n, 2000, replace=False)
     e = np.linalg.norm(sc[rows, :20] - osc[rows, :20]) / np.linalg.norm(osc[rows, :20])
     assert e <= 1e-4, e
+
+
+def test_pca_rank_deficient(dev):
+    # X of rank 5 (plus the offset): the 64-column subspace is rank 5, its
+    # Gram matrix singular -- the shifted first CholeskyQR pass must carry
+    # it; the 5 nonzero singular values and their components match the
+    # oracle, the rest are ~0, and everything stays finite and orthonormal
+    say("pca rank 5")
+    n, g, k = 3000, 200, 10
+    X = synth.make_expression(n, g, 41, latent=5, top=50.0, bottom=5.0, noise=0.0)
+    Om = synth.make_omega(g, 42)
+    sc, comp, sv, mu = run(dev, X, k, Om, 2)
+    osc, ocomp, osv, omu = opca.randomized_pca(X.astype(np.float64), k, Om.astype(np.float64), 2)
+    assert np.isfinite(sc).all() and np.isfinite(comp).all() and np.isfinite(sv).all()
+    np.testing.assert_allclose(sv[:5], osv[:5], rtol=1e-4)
+    assert np.all(sv[5:] <= 1e-3 * sv[0]), sv
+    dots = np.abs(np.sum(comp[:5] * ocomp[:5], axis=1))
+    assert np.all(dots > 1 - 1e-4), dots
+    np.testing.assert_allclose(comp @ comp.T, np.eye(k), atol=1e-3)

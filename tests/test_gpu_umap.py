@@ -195,3 +195,25 @@ def test_umap_gather_epochs_equal_scatter_large(dev):
     A = api.umap_layout(Y0.clone(), G, 0.583, 1.334, 200, epochs=(0, 6), seed=3, symmetric=True)
     B = api.umap_layout(Y0.clone(), G, 0.583, 1.334, 200, epochs=(0, 6), seed=3, symmetric=False)
     assert torch.equal(A, B) and not torch.equal(A, Y0)
+
+
+def test_umap_smallest_graph_and_most_negatives(dev):
+    # n = 3, k = 2 (the smallest kNN graph), and neg_rate at its maximum of 64
+    say("umap n=3, neg 64")
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 2.0]], np.float32)
+    idx, d2 = oracle.knn(X, 2)
+    d2f = d2.astype(np.float32)
+    rho, sigma, w = U.smooth_knn(np.sqrt(d2f.astype(np.float64)))
+    g_rho, g_sigma, g_w = (t.cpu().numpy().astype(np.float64) for t in api.umap_weights(to_dev(d2f, dev)))
+    # k = 2: the target sum log2(2) = 1 leaves the second weight ~1e-49,
+    # below FP32's smallest subnormal, so the GPU stores 0 there
+    np.testing.assert_allclose(g_w, w, rtol=2e-7, atol=1e-30)
+    wf, rp, col, val = union_inputs(idx, w)
+    G = gpu_union(dev, idx, wf)
+    np.testing.assert_array_equal(G.col.cpu().numpy(), col)
+    Y0 = synth.umap_init(3, 5)
+    valf = val.astype(np.float32)
+    Gd = api.SparseP(to_dev(rp, dev), to_dev(col, dev), to_dev(valf, dev), None, 3)
+    Yg = api.umap_layout(to_dev(Y0, dev), Gd, 1.5, 0.9, 20, 1.0, 64, seed=7, epochs=(10, 12))
+    Yo = U.layout(Y0.astype(np.float64), rp, col, valf, 20, 1.5, 0.9, 1.0, 64, 7, epochs=(10, 12))
+    assert np.abs(Yg.cpu().numpy() - Yo).max() <= 2 * step_tol(Y0, Yo)
