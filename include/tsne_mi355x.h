@@ -427,7 +427,8 @@ int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, const int32_t*
  * the timestamps, "stop" at the end.  Both files are created (truncated)
  * and flushed row by row.
  *   period_s in [1e-3, 3600]; pid >= 0; *out receives the handle.
- *   Errors: TSNE_ERR_INVALID_ARG (bad argument, a file cannot be opened).
+ *   Errors: TSNE_ERR_INVALID_ARG (bad argument, a file cannot be opened,
+ *   or no thread could be started).
  * tsne_monitor_timestamp -- appends (now, name) to the events; commas,
  *   quotes and line breaks in name become '_'.  Thread-safe.
  * tsne_monitor_has_gpu -- 1 when the GPU columns are being sampled.

@@ -267,7 +267,15 @@ extern "C" int tsne_monitor_start(double period_s, int32_t hip_device, int32_t p
   std::fputs("t_s,name\n", m->events);
   m->t0 = tsne::mon::Clock::now();
   m->event("start");
-  m->worker = std::thread([m] { m->run(); });
+  try {
+    m->worker = std::thread([m] { m->run(); });
+  } catch (...) {  // no thread to be had: no exception crosses the ABI
+    std::fclose(m->samples);
+    std::fclose(m->events);
+    m->smi.close();
+    delete m;
+    return TSNE_ERR_INVALID_ARG;
+  }
   *out = m;
   return TSNE_OK;
 }
