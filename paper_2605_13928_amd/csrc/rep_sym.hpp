@@ -5,11 +5,16 @@
 // That halves the reciprocals and differences of the ordered-pair sweep.
 //
 // Decomposition.  Points are cut into superblocks of S (a multiple of 256);
-// a job is one superblock pair (s, t), s <= t, off-diagonal pairs first.  A
-// persistent grid of P workgroups takes jobs round robin (job q goes to
-// workgroup q mod P), so each workgroup's job list, and with it every sum,
-// is fixed; while it computes one job it already loads the points of its
-// next one into registers.  A workgroup has 4 waves; a wave tile is 64
+// a job is one superblock pair (s, t), s <= t, numbered off-diagonal pairs
+// first (job_pair).  A persistent grid of P workgroups deals the jobs in
+// rounds of P, heaviest first (sym_sched: the full off-diagonal jobs, then
+// the diagonal jobs and the jobs against the last, partly filled superblock
+// in the order of their cost, the last diagonal job at the end), forward
+// over the workgroups in even rounds and backward in odd ones, so that a
+// workgroup that got a heavier job in one round gets a lighter one in the
+// next.  Each workgroup's job list, and with it every sum, is fixed; while
+// it computes one job it already loads the points of its next one into
+// registers.  A workgroup has 4 waves; a wave tile is 64
 // i-points x 64 j-points on an 8 x 8 lane grid: lane (a, b) = lane (8a + b)
 // holds i-points 8a..8a+7 and j-points 8b..8b+7 in registers and evaluates
 // their 64 pairs with no data movement.  Each wave sweeps its i-subblocks
@@ -24,9 +29,12 @@
 // first).  A later pass sums the ns partials of a row in index
 // order, and the P per-workgroup Z sums in index order, so the result is
 // deterministic.
-// In the diagonal superblock, tiles below the diagonal are skipped and the
-// 64 x 64 diagonal tiles take every ordered pair on the i side only, with
-// the self pair masked.  Points past n are placed far away,
+// In the diagonal superblock each unordered pair of subblocks {u, v} is one
+// tile, taken by the wave of the subblock whose cyclic distance to the other
+// is the shorter (u takes v = u + 1 ... u + nsub/2 mod nsub, the distance
+// nsub/2 only for u < nsub/2), so that its waves carry nearly equal shares;
+// the 64 x 64 diagonal tiles take every ordered pair on the i side only,
+// with the self pair masked.  Points past n are placed far away,
 // each at its own position, so all their weights are exactly 0.
 #pragma once
 
@@ -175,6 +183,18 @@ __device__ __forceinline__ void job_pair(int64_t q, int64_t ns, int64_t& s, int6
   s = q - tt * (tt - 1) / 2;
 }
 
+// Job at position pos of the dealing order: jobs [0, nF) are the full
+// off-diagonal pairs (t < ns - 1), then the ns - 1 diagonal jobs s < ns - 1
+// (cost per wave about nsub / 2 tiles) and the ns - 1 jobs (s, ns - 1)
+// against the last superblock (nj_last tiles per subblock), the costlier
+// class first, then the last diagonal job.  In job_pair's numbering the
+// last-superblock jobs are [nF, noff) and the diagonal ones [noff, njobs).
+__device__ __forceinline__ int64_t sym_sched(int64_t pos, int64_t ns, bool last_first) {
+  const int64_t nF = (ns - 1) * (ns - 2) / 2, noff = ns * (ns - 1) / 2;
+  if (last_first || pos < nF || pos == noff + ns - 1) return pos;
+  return pos < nF + ns - 1 ? noff + (pos - nF) : pos - (ns - 1);
+}
+
 // One 64 x 64 wave tile.  DIAG: i and j blocks coincide; all ordered pairs
 // go to the i side, self pairs masked, Z weight 1 (else 2, via the caller).
 template <bool DIAG, bool ZROW>
@@ -315,8 +335,16 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
     }
   };
 
-  int64_t q = blockIdx.x;
-  if (q < njobs) {
+  // this workgroup's job of round r, or -1 past the last
+  const int64_t nj_last = min(int64_t(nsub), (n - (ns - 1) * S + 63) / 64);
+  const bool last_first = 2 * nj_last > nsub + 1;
+  auto job_at = [&](int64_t r) -> int64_t {
+    const int64_t pos = r * P + ((r & 1) ? P - 1 - int64_t(blockIdx.x) : int64_t(blockIdx.x));
+    return pos < njobs ? sym_sched(pos, ns, last_first) : -1;
+  };
+  int64_t round = 0;
+  int64_t q = job_at(0);
+  if (q >= 0) {
     fetch(q);
     if (ATT_PRE) {
       fetch_range(q);
@@ -328,8 +356,9 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
   if (ATT_SEP && ATT)
     for (int u = tid; u < 4 * S; u += 256) aacc[u] = 0ull;
   double zsum = 0.0;
-  for (; q < njobs; q += P) {
+  for (; q >= 0; q = job_at(++round)) {
     const int64_t s = fs, t = ft;  // job q, decoded by its fetch
+    const int64_t qn = job_at(round + 1);
     const bool diag_sb = s == t;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
@@ -338,7 +367,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       jpts[u] = pj[k];
     }
     __syncthreads();  // points staged, accumulators zeroed
-    if (q + P < njobs) fetch(q + P);  // lands while this job computes
+    if (qn >= 0) fetch(qn);  // lands while this job computes
 
     if (ATT) {
       // Attraction of the job's P entries, A_i += p w (y_i - y_j) and
@@ -351,7 +380,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       const int64_t ae0 = ne0, ae1 = ne1;
       const uint32_t pk0 = npk[0], pk1 = npk[1];
       const float pv0 = npv[0], pv1 = npv[1];
-      if (ATT_PRE && q + P < njobs) fetch_range(q + P);  // used after the tiles
+      if (ATT_PRE && qn >= 0) fetch_range(qn);  // used after the tiles
       auto add_entry = [&](uint32_t pk, float pv) {
         const int il = int(pk & 0xFFFFu), jl = int(pk >> 16);
         const float2 yi = ipts[il], yj = jpts[jl];
@@ -399,11 +428,36 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       double di[2] = {0.0, 0.0}, dz = 0.0;
 #pragma unroll
       for (int r = 0; r < 8; ++r) rix[r] = riy[r] = zi[r] = 0.0f;
-      const int v0 = diag_sb ? us : 0;
+      // fold the i-side sums into FP64 (after an 8-lane reduce)
+      auto fold = [&]() {
+        float vi[16];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          vi[r] = rix[r];
+          vi[8 + r] = riy[r];
+          rix[r] = riy[r] = 0.0f;
+        }
+        float o0, o1;
+        rs16_lo(vi, o0, o1);
+        di[0] += double(o0);
+        di[1] += double(o1);
+        if (ZROW) {
+          const float oz = rs8_lo(zi);
+          dz += double(oz);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) zi[r] = 0.0f;
+        }
+      };
+      // tiles of this subblock: j-subblocks 0 .. nj_end - 1, or in the
+      // diagonal superblock us, us + 1, ... (mod nsub), cyclic distance up
+      // to nsub / 2, taken only for us < nsub / 2 (every unordered pair once)
+      const int ntile = diag_sb ? (us < nsub / 2 ? nsub / 2 + 1 : nsub / 2) : nj_end;
       int since_fold = 0;
       const int comp = lane >> 5;
       const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
-      for (int v = v0; v < nj_end; ++v) {
+      for (int e = 0; e < ntile; ++e) {
+        const int v = diag_sb ? (us + e < nsub ? us + e : us + e - nsub) : e;
+        if (v >= nj_end) continue;  // past the last point (partly filled superblock)
         float4 jc[4];
         {
           const float4* p = reinterpret_cast<const float4*>(jpts + 64 * v + 8 * b);
@@ -433,28 +487,12 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
             myj[2 * S + 64 * v + 8 * b + cz] += oz;
           }
         }
-        // fold the i-side sums into FP64 every 8 tiles (after an 8-lane reduce)
-        if (++since_fold == 8 || v == nj_end - 1) {
+        if (++since_fold == 8) {
           since_fold = 0;
-          float vi[16];
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            vi[r] = rix[r];
-            vi[8 + r] = riy[r];
-            rix[r] = riy[r] = 0.0f;
-          }
-          float o0, o1;
-          rs16_lo(vi, o0, o1);
-          di[0] += double(o0);
-          di[1] += double(o1);
-          if (ZROW) {
-            const float oz = rs8_lo(zi);
-            dz += double(oz);
-#pragma unroll
-            for (int r = 0; r < 8; ++r) zi[r] = 0.0f;
-          }
+          fold();
         }
       }
+      if (since_fold) fold();
       // i side of this subblock -> LDS (each point owned by exactly one wave)
       {
         const int comp = (lane >> 2) & 1;
@@ -469,7 +507,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
       }
     }
     // the next job's first attraction entries (its range arrived meanwhile)
-    if (ATT_PRE && q + P < njobs) fetch_entries();
+    if (ATT_PRE && qn >= 0) fetch_entries();
     __syncthreads();  // job's accumulators complete; staged points free
 
     // write the partials part[t][i in s] and part[s][j in t]; each thread
