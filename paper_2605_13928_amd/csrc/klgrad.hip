@@ -285,37 +285,82 @@ __device__ __forceinline__ int64_t job_of(int64_t s, int64_t t, int64_t ns) {
   return s == t ? ns * (ns - 1) / 2 + s : t * (t - 1) / 2 + s;  // inverse of job_pair
 }
 
-// One wave per row i: entries (i, j) with j > i, counted per job.
-__global__ __launch_bounds__(256) void att_count_kernel(int64_t n, int64_t S, int64_t ns,
-                                                        const int64_t* __restrict__ row_ptr,
-                                                        const int32_t* __restrict__ col, int* __restrict__ cnt) {
-  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  for (int64_t e = row_ptr[i] + lane_id(); e < row_ptr[i + 1]; e += 64) {
-    const int32_t j = col[e];
-    if (j > i && j < n) atomicAdd(&cnt[job_of(i / S, j / S, ns)], 1);
-  }
+// Blocks of ATT_ROWS consecutive rows; S is a multiple of ATT_ROWS, so a
+// block's rows lie in one superblock s and an entry (i, j), j > i, belongs
+// to job (s, j / S).  The block histograms its entries over the opposite
+// superblock t in LDS, ATT_BINS superblocks per pass, and touches each job's
+// global counter once per pass: a few global atomics per block instead of
+// one per entry.  The order of the entries inside a job's range follows the
+// LDS atomics; the all-pairs kernel sums them in exact fixed point, so the
+// order does not reach any result.
+constexpr int ATT_ROWS = 16;
+constexpr int ATT_BINS = 512;
+
+// row of entry e among the block's rows (rp[0..ATT_ROWS]); e is increasing
+// per thread, so the search resumes from the previous row
+__device__ __forceinline__ int att_row(const int64_t* rp, int64_t e, int r) {
+  while (r < ATT_ROWS - 1 && rp[r + 1] <= e) ++r;
+  return r;
 }
 
-__global__ __launch_bounds__(256) void att_scatter_kernel(int64_t n, int64_t S, int64_t ns,
-                                                          const int64_t* __restrict__ row_ptr,
-                                                          const int32_t* __restrict__ col,
-                                                          const float* __restrict__ val,
-                                                          const int64_t* __restrict__ off, int* __restrict__ cur,
-                                                          uint32_t* __restrict__ ij, float* __restrict__ p,
-                                                          int64_t cap) {
-  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  for (int64_t e = row_ptr[i] + lane_id(); e < row_ptr[i + 1]; e += 64) {
-    const int32_t j = col[e];
-    if (j > i && j < n) {
-      const int64_t s = i / S, t = j / S, q = job_of(s, t, ns);
-      const int64_t pos = off[q] + atomicAdd(&cur[q], 1);
-      if (pos < cap) {  // cap < entries only if the caller's nnz is wrong
-        ij[pos] = uint32_t(i - s * S) | (uint32_t(j - t * S) << 16);
-        p[pos] = val[e];
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void att_bucket_kernel(int64_t n, int64_t S, int64_t ns,
+                                                         const int64_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const float* __restrict__ val, int* __restrict__ cnt,
+                                                         const int64_t* __restrict__ off, int* __restrict__ cur,
+                                                         uint32_t* __restrict__ ij, float* __restrict__ p, int64_t cap) {
+  __shared__ int h[ATT_BINS];
+  __shared__ int64_t base[SCATTER ? ATT_BINS : 1];
+  __shared__ int64_t rp[ATT_ROWS + 1];
+  const int tid = threadIdx.x;
+  const int64_t r0 = int64_t(blockIdx.x) * ATT_ROWS;
+  const int64_t s = r0 / S;
+  if (tid <= ATT_ROWS) rp[tid] = row_ptr[r0 + tid < n ? r0 + tid : n];
+  __syncthreads();
+  const int64_t E0 = rp[0], E1 = rp[ATT_ROWS];
+  for (int64_t w0 = s; w0 < ns; w0 += ATT_BINS) {  // opposite superblocks t >= s
+    const int64_t w1 = w0 + ATT_BINS < ns ? w0 + ATT_BINS : ns;
+    for (int b = tid; b < ATT_BINS; b += 256) h[b] = 0;
+    __syncthreads();
+    int r = 0;
+    for (int64_t e = E0 + tid; e < E1; e += 256) {
+      r = att_row(rp, e, r);
+      const int64_t i = r0 + r;
+      const int32_t j = col[e];
+      const int64_t t = j / S;
+      if (j > i && j < n && t >= w0 && t < w1) atomicAdd(&h[t - w0], 1);
+    }
+    __syncthreads();
+    for (int64_t t = w0 + tid; t < w1; t += 256) {
+      const int c = h[t - w0];
+      if (!c) continue;
+      const int64_t q = job_of(s, t, ns);
+      if (SCATTER) {
+        base[t - w0] = off[q] + atomicAdd(&cur[q], c);
+        h[t - w0] = 0;  // becomes the block's cursor in the range
+      } else {
+        atomicAdd(&cnt[q], c);
       }
     }
+    if (SCATTER) {
+      __syncthreads();
+      r = 0;
+      for (int64_t e = E0 + tid; e < E1; e += 256) {
+        r = att_row(rp, e, r);
+        const int64_t i = r0 + r;
+        const int32_t j = col[e];
+        const int64_t t = j / S;
+        if (j > i && j < n && t >= w0 && t < w1) {
+          const int64_t pos = base[t - w0] + atomicAdd(&h[t - w0], 1);
+          if (pos < cap) {  // cap < entries only if the caller's nnz is wrong
+            ij[pos] = uint32_t(i - s * S) | (uint32_t(j - t * S) << 16);
+            p[pos] = val[e];
+          }
+        }
+      }
+    }
+    __syncthreads();  // h and base are reused by the next pass
   }
 }
 
@@ -344,12 +389,15 @@ int att_build(const AttPlan& A, const SymGrid& g, char* ws, int64_t n, const int
   int rc;
   if ((rc = launch_fill<int>(cnt, g.njobs, 0, s))) return rc;
   if ((rc = launch_fill<int>(cur, g.njobs, 0, s))) return rc;
-  const dim3 grid(unsigned(ceil_div(n, 4))), block(256);
-  hipLaunchKernelGGL(att_count_kernel, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, cnt);
+  const dim3 grid(unsigned(ceil_div(n, ATT_ROWS))), block(256);
+  hipLaunchKernelGGL(att_bucket_kernel<false>, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, val, cnt,
+                     static_cast<const int64_t*>(nullptr), static_cast<int*>(nullptr),
+                     static_cast<uint32_t*>(nullptr), static_cast<float*>(nullptr), int64_t(0));
   TSNE_CHECK_LAUNCH();
   if ((rc = exclusive_scan<int>(cnt, g.njobs, off, bsum, s))) return rc;
   const int64_t cap = int64_t((A.o_p - A.o_ij) / sizeof(uint32_t));
-  hipLaunchKernelGGL(att_scatter_kernel, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, val, off, cur, ij, p, cap);
+  hipLaunchKernelGGL(att_bucket_kernel<true>, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, val,
+                     static_cast<int*>(nullptr), off, cur, ij, p, cap);
   TSNE_CHECK_LAUNCH();
   *out = AttList{off, ij, p, cap};
   return TSNE_OK;

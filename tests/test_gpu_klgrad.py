@@ -47,7 +47,9 @@ def test_klgrad_c1(dev, alpha, ystd):
     compare(dev, S, Y, alpha)
 
 
-@pytest.mark.parametrize("n", [2, 3, 97, 1024, 1025, 4097])
+# 4161 and 4225 leave 2 and 3 subblocks in the last superblock of 256, so the
+# jobs are dealt with the diagonal ones before, resp. after, the jobs against it
+@pytest.mark.parametrize("n", [2, 3, 97, 1024, 1025, 4097, 4161, 4225])
 def test_klgrad_ragged_sizes(dev, n):
     say("klgrad ragged", n)
     k = min(30, n - 1)
@@ -76,11 +78,14 @@ def test_klgrad_c2_full_size(dev):
         compare(dev, S, Y, alpha, zrow=False)
 
 
-def test_klgrad_c5_sampled_rows(dev):
-    # full scale n = 1,000,000: per-row Z_i and gradient rows checked on a
-    # seeded sample of rows, plus sum_i Z_i = Z (a property at any size).
-    say("klgrad c5 sampled")
-    n = 1_000_000
+# 1,000,000 is the full-scale workload (superblocks of 1024); 49,864 and
+# 99,628 (superblocks of 512 and 1024) leave 4 and 5 subblocks in the last
+# superblock, which deals the diagonal jobs before the jobs against it.
+@pytest.mark.parametrize("n", [49_864, 99_628, 1_000_000])
+def test_klgrad_sampled_rows(dev, n):
+    # per-row Z_i and gradient rows checked on a seeded sample of rows, plus
+    # sum_i Z_i = Z (a property at any size).
+    say("klgrad sampled", n)
     idx, d2, Pc, S = random_graph_P(n, 90, 30.0, 5)
     v32 = S.val.astype(np.float32)
     So = widen(S, v32)
@@ -90,7 +95,7 @@ def test_klgrad_c5_sampled_rows(dev):
     Zr = Zr.cpu().numpy()
     Zg = Z.item()
     assert abs(Zr.sum() - Zg) <= 1e-9 * Zg
-    rows = np.random.default_rng(5).choice(n, 192, replace=False)
+    rows = np.random.default_rng(5 + n).choice(n, 192, replace=False)
     Zo, Ro, Ao = oracle.grad_rows(Y.astype(np.float64), rows, So)
     np.testing.assert_allclose(Zr[rows], Zo, rtol=1e-6)
     # g_i = 4 (A_i - R_i / Z) with the oracle's A_i, R_i; Z from the checked row sums
@@ -99,15 +104,27 @@ def test_klgrad_c5_sampled_rows(dev):
     assert e <= GRAD_RTOL, e
 
 
-@pytest.mark.parametrize("n", [20_000, 50_000, 100_003])
+def test_fused_attraction_full_scale(dev):
+    # n = 1,000,000: 977 superblocks, so the bucketing of P's entries by job
+    # takes its opposite superblocks in more than one LDS window (the graph
+    # is the one of the sampled-rows test above, still cached)
+    fused_first_iteration(dev, 1_000_000, 5)
+
+
+@pytest.mark.parametrize("n", [20_000, 49_864, 50_000, 99_628, 100_003])
 def test_fused_attraction_first_iteration(dev, n):
     # tsne_optimize sums the attraction inside the all-pairs kernel (one
-    # launch configuration per superblock size: 256, 512, 1024 here).  At
-    # t = 0 the update is -lr * 0.8 * g exactly up to FP32 rounding, so the
-    # gradient is recovered from it and checked row by row against the
+    # launch configuration per superblock size: 256, 512 (49,864, 50,000),
+    # 1024 (99,628, 100,003) here; the pairs differ in the dealing order).
+    fused_first_iteration(dev, n, 7)
+
+
+def fused_first_iteration(dev, n, seed):
+    # At t = 0 the update is -lr * 0.8 * g exactly up to FP32 rounding, so
+    # the gradient is recovered from it and checked row by row against the
     # oracle's A_i, R_i (alpha = 12), with Z from tsne_kl_grad at the same Y.
     say("fused attraction", n)
-    idx, d2, Pc, S = random_graph_P(n, 90, 30.0, 7)
+    idx, d2, Pc, S = random_graph_P(n, 90, 30.0, seed)
     So = widen(S, S.val.astype(np.float32))
     P = sparse_to_dev(So, dev)
     Y = synth.random_embedding(n, 5.0, 3000 + n % 97)
