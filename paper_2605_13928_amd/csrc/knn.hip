@@ -155,16 +155,24 @@ __device__ void emit_row(const uint64_t* __restrict__ buf, int c, int keep, int3
 }
 
 // ---------------------------------------------------------------------
-// FP32 exact path.  Block = 4 waves x 16 rows; each step covers 128
+// FP32 exact path.  Block = 4 waves x RW rows (RW = 16, or 8 where that
+// gives the busiest CU fewer rows: fknn_small_blocks); each step covers 128
 // columns, 2 per lane; the rows' coordinates are LDS broadcasts, the
-// columns' are per-lane LDS reads, dimension chunks of 64.
+// columns' are per-lane LDS reads, dimension chunks of 56.
 
-constexpr int F_RW = 16;
-constexpr int F_ROWS = 64;
 constexpr int F_COLS = 128;
 constexpr int F_DC = 56;
-constexpr int XI_S = F_ROWS + 4;  // LDS row strides: multiples of 4 floats keep the
-constexpr int XJ_S = F_COLS + 4;  // 16-byte reads aligned and spread the stores' banks
+constexpr int XJ_S = F_COLS + 4;  // LDS row strides: multiples of 4 floats keep the
+                                  // 16-byte reads aligned and spread the stores' banks
+// Three blocks of either size are resident per CU (LDS and registers), on
+// 256 CUs.  32-row blocks are taken when all of them are resident at once
+// and the CU with the most blocks then holds fewer rows than with 64-row
+// blocks (20 k points: 3 x 32 = 96 rows against 2 x 64 = 128).
+constexpr int64_t F_CUS = 256, F_RESIDENT = 3;
+inline bool fknn_small_blocks(int64_t n) {
+  const int64_t b8 = ceil_div(n, 32), b16 = ceil_div(n, 64);
+  return b8 <= F_CUS * F_RESIDENT && ceil_div(b8, F_CUS) * 32 < ceil_div(b16, F_CUS) * 64;
+}
 
 // Stage rows [r0, r0 + nrows) x dims [dc, dc + dl) of X transposed into
 // dst[c * stride + r]: one row per wave instruction (coalesced), rows past
@@ -188,10 +196,13 @@ __device__ __forceinline__ void stage_rows_t(float* __restrict__ dst, int stride
   }
 }
 
-template <int EPL>
+template <int EPL, int F_RW>
 __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__ X, int64_t n, int d, int k,
                                                        uint64_t* __restrict__ bufs, int32_t* __restrict__ out_idx,
                                                        float* __restrict__ out_d2) {
+  static_assert(F_RW == 8 || F_RW == 16, "rows per wave");
+  constexpr int F_ROWS = 4 * F_RW;
+  constexpr int XI_S = F_ROWS + 4;
   constexpr int CAP = 64 * EPL;
   __shared__ __attribute__((aligned(16))) float xi_s[F_DC * XI_S];
   __shared__ __attribute__((aligned(16))) float xj_s[F_DC * XJ_S];
@@ -218,9 +229,15 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
       __syncthreads();
       for (int c = 0; c < dl; ++c) {
         const float4* ap = reinterpret_cast<const float4*>(&xi_s[c * XI_S + w * F_RW]);
-        const float4 a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
-        const float a[F_RW] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
-                               a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
+        float a[F_RW];
+#pragma unroll
+        for (int q4 = 0; q4 < F_RW / 4; ++q4) {
+          const float4 v = ap[q4];
+          a[4 * q4] = v.x;
+          a[4 * q4 + 1] = v.y;
+          a[4 * q4 + 2] = v.z;
+          a[4 * q4 + 3] = v.w;
+        }
         const float2 b = *reinterpret_cast<const float2*>(&xj_s[c * XJ_S + lane * 2]);
 #pragma unroll
         for (int r = 0; r < F_RW; ++r) {
@@ -575,8 +592,12 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   uint64_t* bufs = reinterpret_cast<uint64_t*>(ws + L.o_buf);
   hipStream_t s = as_stream(stream);
   if (precision == TSNE_KNN_FP32) {
-    const dim3 grid(unsigned(ceil_div(n, F_ROWS)));
-    hipLaunchKernelGGL(knn_fp32_kernel<8>, grid, dim3(256), 0, s, X, n, d, k, bufs, nbr_idx, nbr_d2);
+    if (fknn_small_blocks(n))
+      hipLaunchKernelGGL((knn_fp32_kernel<8, 8>), dim3(unsigned(ceil_div(n, 32))), dim3(256), 0, s, X, n, d, k, bufs,
+                         nbr_idx, nbr_d2);
+    else
+      hipLaunchKernelGGL((knn_fp32_kernel<8, 16>), dim3(unsigned(ceil_div(n, 64))), dim3(256), 0, s, X, n, d, k, bufs,
+                         nbr_idx, nbr_d2);
     TSNE_CHECK_LAUNCH();
     return TSNE_OK;
   }

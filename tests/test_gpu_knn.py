@@ -76,9 +76,11 @@ def test_knn_massive_ties(dev):
     assert all(len(set(r)) == k for r in bi.tolist())
 
 
-def test_knn_fp32_c2_sampled_rows(dev):
-    say("knn fp32 c2 full")
-    X, _ = synth.make_points("c2")
+# 20,000 (the c2 workload) runs 32-row blocks, 30,000 (c2 shape) 64-row ones
+@pytest.mark.parametrize("n", [20_000, 30_000])
+def test_knn_fp32_c2_sampled_rows(dev, n):
+    say("knn fp32 c2 shape", n)
+    X, _ = synth.make_points("c2", n=n)
     gi, gd = gpu_knn(dev, X, 90)
     rows = np.random.default_rng(2).choice(X.shape[0], 400, replace=False)
     oi, od = oracle.knn(X, 90, rows=rows)
