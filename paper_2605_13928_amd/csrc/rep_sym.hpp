@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
     const int64_t pos = r * P + ((r & 1) ? P - 1 - int64_t(blockIdx.x) : int64_t(blockIdx.x));
     return pos < njobs ? sym_sched(pos, ns, last_first) : -1;
   };
-  int64_t round = 0;
+  int64_t rnd = 0;
   int64_t q = job_at(0);
   if (q >= 0) {
     fetch(q);
@@ -356,9 +356,9 @@ __global__ __launch_bounds__(256) void rep_sym_kernel(const float2* __restrict__
   if (ATT_SEP && ATT)
     for (int u = tid; u < 4 * S; u += 256) aacc[u] = 0ull;
   double zsum = 0.0;
-  for (; q >= 0; q = job_at(++round)) {
+  for (; q >= 0; q = job_at(++rnd)) {
     const int64_t s = fs, t = ft;  // job q, decoded by its fetch
-    const int64_t qn = job_at(round + 1);
+    const int64_t qn = job_at(rnd + 1);
     const bool diag_sb = s == t;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
