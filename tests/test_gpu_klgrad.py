@@ -142,3 +142,24 @@ def fused_first_iteration(dev, n, seed):
     assert e <= GRAD_RTOL, e
     # and the step itself: Y + update
     np.testing.assert_array_equal(Yo.cpu().numpy(), (Yd + U).cpu().numpy())
+
+
+def test_fused_loop_bitwise_reproducible_c2(dev):
+    # The job-grouped copy of P is filled through LDS atomics, so the order
+    # of the entries inside a job's range changes from call to call; the
+    # all-pairs kernel sums them in exact 64-bit fixed point, so two runs
+    # of the loop from the same state must agree bit for bit.
+    say("fused loop determinism c2")
+    n = 20_000
+    idx, d2, Pc, S = random_graph_P(n, 90, 30.0, 2)
+    P = sparse_to_dev(widen(S, S.val.astype(np.float32)), dev)
+    Y0 = to_dev(synth.random_embedding(n, 1e-2, 2024), dev)
+    runs = []
+    for _ in range(2):
+        Y = Y0.clone()
+        U = torch.zeros_like(Y)
+        G = torch.ones_like(Y)
+        api.optimize(Y, U, G, P, 0, 30, lr=200.0, exaggeration=12.0)
+        runs.append((Y.cpu(), U.cpu(), G.cpu()))
+    for a, b in zip(runs[0], runs[1]):
+        assert torch.equal(a, b)
