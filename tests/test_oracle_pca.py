@@ -4,7 +4,9 @@ values and components are those of the full SVD of the centred matrix,
 numpy.linalg.svd); with a spectral gap and power iterations the leading
 singular values converge to the full SVD's; components are orthonormal and
 the scores are the centred data projected on them; the mean is the column
-mean; the sign convention holds."""
+mean; the sign convention holds; on a full-rank matrix the estimates
+interlace below the true singular values and the rank-k reconstruction
+error is at least the (k+1)-th singular value (Eckart-Young)."""
 import numpy as np
 import pytest
 
@@ -66,3 +68,19 @@ def test_orth_is_unique_qr_factor():
     np.testing.assert_allclose(Q.T @ Q, np.eye(6), atol=1e-13)
     R = Q.T @ Y
     assert np.all(np.diag(R) > 0) and np.abs(np.tril(R, -1)).max() < 1e-12
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_singular_values_interlace_and_eckart_young(q):
+    # On a full-rank noisy matrix, for any q: the estimates are the singular
+    # values of Q^T Xc with Q orthonormal, so s_i(estimate) <= s_i(Xc)
+    # (interlacing), and no rank-k reconstruction beats the truncated SVD
+    # (Eckart-Young): ||Xc - scores components||_2 >= s_{k+1}(Xc).
+    X = low_rank(300, 80, 40, 11, noise=2.0)
+    k, l = 10, 16
+    Om = np.random.default_rng(3).standard_normal((80, l))
+    sc, comp, sv, mu = pca.randomized_pca(X, k, Om, q=q)
+    s, _ = full_svd(X)
+    assert np.all(sv <= s[:k] * (1 + 1e-12))
+    err = np.linalg.norm((X - mu) - sc @ comp, 2)
+    assert err >= s[k] * (1 - 1e-12)
