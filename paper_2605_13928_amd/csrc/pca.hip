@@ -379,10 +379,11 @@ __global__ __launch_bounds__(64) void pca_gram_reduce_kernel(const double* __res
 // the trailing update of the upper triangle.  Thread t owns the entries
 // (t / 64 + 4 u, t % 64), u < 16, of every update; it loads all of them
 // before it stores any, so one LDS round trip serves a whole step.  The
-// inverse: R X = I for all 64 right-hand sides at once, by column-oriented
-// back substitution (per i, row i of X divided by R[i][i], then its multiples
-// taken off the rows above).  Rinv (float, 64 x 64 row-major) is the W of
-// the next product Q = Y Rinv.
+// inverse comes from the same pass: the row operations that take G to R
+// (row i minus R[j][i] times the scaled row j, row j divided by R[j][j])
+// form the matrix E with E G = R, i.e. E = R^-T; applied to X = I alongside,
+// they leave X = R^-T (lower triangular).  Rinv = X^T (float, 64 x 64
+// row-major) is the W of the next product Q = Y Rinv.
 __global__ __launch_bounds__(256) void pca_cholinv_kernel(const double* __restrict__ Gin, double shift,
                                                           float* __restrict__ Rinv) {
   constexpr int NU = PCA_L * PCA_L / 256;
@@ -401,47 +402,36 @@ __global__ __launch_bounds__(256) void pca_cholinv_kernel(const double* __restri
     __syncthreads();
   }
   for (int j = 0; j < PCA_L; ++j) {
-    // row j of R: every thread of the first wave takes the pivot itself
-    if (tid < PCA_L && tid >= j) {
+    // row j of R and row j of X divided by the pivot: every thread of the
+    // first wave takes the pivot itself (lane c: R[j][c] for c >= j, X[j][c]
+    // for c <= j, the only nonzeros of that row of X)
+    if (tid < PCA_L) {
       const double d = A[j][j];
       const double rjj = sqrt(d > 1e-300 ? d : 1e-300);
       const double v = tid == j ? rjj : A[j][tid] / rjj;
+      const double x = X[j][tid] / rjj;
       __builtin_amdgcn_wave_barrier();  // every lane has read A[j][j] before lane j replaces it
-      A[j][tid] = v;
+      if (tid >= j) A[j][tid] = v;
+      if (tid <= j) X[j][tid] = x;
     }
     __syncthreads();
-    double rji[NU], aic[NU];
-    const double rjc = A[j][c];
+    double rji[NU], aic[NU], xic[NU];
+    const double rjc = A[j][c], xjc = X[j][c];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       rji[u] = A[j][r0 + 4 * u];
       aic[u] = A[r0 + 4 * u][c];
+      xic[u] = X[r0 + 4 * u][c];
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int i = r0 + 4 * u;
       if (i > j && c >= i) A[i][c] = aic[u] - rji[u] * rjc;
+      if (i > j && c <= j) X[i][c] = xic[u] - rji[u] * xjc;
     }
     __syncthreads();
   }
-  for (int i = PCA_L - 1; i >= 0; --i) {
-    const double xi = X[i][c] / A[i][i];
-    double rpi[NU], xpc[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      rpi[u] = A[r0 + 4 * u][i];
-      xpc[u] = X[r0 + 4 * u][c];
-    }
-    __syncthreads();  // row i of X read by every thread before it is replaced
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const int p = r0 + 4 * u;
-      if (p < i) X[p][c] = xpc[u] - rpi[u] * xi;
-    }
-    if (r0 == 0) X[i][c] = xi;
-    __syncthreads();
-  }
-  for (int e = tid; e < PCA_L * PCA_L; e += 256) Rinv[e] = float(X[e / PCA_L][e % PCA_L]);
+  for (int e = tid; e < PCA_L * PCA_L; e += 256) Rinv[e] = float(X[e % PCA_L][e / PCA_L]);
 }
 
 // --- symmetric eigenproblem of the 64 x 64 Gram matrix, one block, FP64 -------
