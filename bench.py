@@ -1,26 +1,40 @@
 """Benchmark of the exact t-SNE hot path on one MI355X.
 
-A step is one pass of the whole path over the workload's synthetic input,
-already resident in HBM: FP32 exact kNN, perplexity calibration,
-symmetrisation, then every gradient + optimiser iteration of the schedule.
-`value` = ordered pair interactions evaluated by the gradient over the timed
-steps / wall time of those steps.  The iterations run through tsne_optimize,
-which records HIP events (on the stream the kernels are launched on) right
-around every 10th launch of the all-pairs repulsion kernel: they give the
-dominant kernel's average per-launch time for the roofline.  Outside the timed region: the BF16-MFMA vs FP32 kNN build
-comparison, and the CPU-baseline leg (the FP64 oracle timed on a bounded
-sample of the same workload, which also yields the error statistics), the
-KL autograd timing, the interpolated (FFT) gradient timed against the
-exact one at the C5 point count, the PCA that produces the embedding's
-input (200k cells x 2000 genes, 50 components, 2 power iterations), and
-UMAP on the C5 points (k = 15 neighbour graph, fuzzy union, 200 epochs).
-Those legs run under the resource monitor (0.1 s samples), whose per-leg
-summary (GPU activity, VRAM, power, CPU) is the record's `telemetry`.  The
-CPU-baseline leg also times the FP64 oracles of the widened rows
-(interpolated repulsion, PCA, one UMAP epoch) on bounded samples of the
-same recipes, beside the GPU figures (`cpu_baseline.widened_rows`).
+The headline workload is the full-scale one: 1,000,000 points x 50
+dimensions shaped like PCA scores of a cell population, BF16-MFMA kNN
+(k = 90, 180 candidates re-ranked in FP32), perplexity 30, then 1000
+iterations of the exact all-pairs gradient and the optimiser step.  Inputs
+are generated and uploaded before anything is timed.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+The one-off affinity stage (kNN, calibration, symmetrisation) runs once and
+is timed on its own with HIP events (`affinity_s`, `knn_build_s`).  A timed
+step is then a slice of `--slice` consecutive iterations of the schedule
+(gradient + step, through tsne_optimize), continuing from where the
+previous step stopped: the warmup steps run iterations [0, W s), the timed
+ones the next K s, so the early-exaggeration phase and the late phase are
+both covered.  For workloads small enough to run whole (n <= 100,000 by
+default) a step is instead the whole path: kNN, calibration,
+symmetrisation and every iteration.  `value` = ordered pair interactions
+evaluated by the gradient over the timed steps / wall time of those steps.
+tsne_optimize records HIP events (on the stream the kernels are launched
+on) right around launches of the all-pairs repulsion kernel: they give the
+dominant kernel's average per-launch time for the roofline.
+
+Outside the timed region: the FP32 exact kNN at the same size (the
+BF16-vs-FP32 build comparison and its agreement), the same comparison at
+the 200,000-point shape, the CPU-baseline leg (the FP64 oracle timed on a
+bounded sample of the same workload, which also yields the error
+statistics), the KL autograd timing, the interpolated (FFT) gradient timed
+against the exact one, the PCA that produces the embedding's input (200k
+cells x 2000 genes, 50 components, 2 power iterations), and UMAP on the
+same points (k = 15 neighbour graph, fuzzy union, 200 epochs).  Those legs
+run under the resource monitor (0.1 s samples), whose per-leg summary (GPU
+activity, VRAM, power, CPU) is the record's `telemetry`.  The CPU-baseline
+leg also times the FP64 oracles of the widened rows (interpolated
+repulsion, PCA, one UMAP epoch) on bounded samples of the same recipes,
+beside the GPU figures (`cpu_baseline.widened_rows`).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5] [--slice S]
 """
 from __future__ import annotations
 
@@ -43,9 +57,13 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c5")
+    ap.add_argument("--slice", type=int, default=None,
+                    help="iterations per timed step (default: the whole path for n <= 100000, else 10)")
+    ap.add_argument("--knn-fp32-same-n", type=int, default=1,
+                    help="also time the FP32 exact kNN at the workload's own size (0: skip)")
     ap.add_argument("--iters", type=int, default=None, help="override the schedule's iteration count")
     ap.add_argument("--knn-compare-n", type=int, default=200_000,
                     help="point count of the BF16-vs-FP32 kNN build comparison (C3 shape)")
@@ -118,12 +136,17 @@ def main():
     w = synth.WORKLOADS[args.workload]
     iters = w.iters if args.iters is None else args.iters
     n = w.n
+    whole = args.slice is None and n <= 100_000
+    sl = iters if whole else (args.slice or 10)
+    if not whole and (args.warmup + args.steps) * sl > iters:
+        print(json.dumps({"error": f"warmup + steps = {args.warmup + args.steps} slices of {sl} iterations "
+                                   f"exceed the schedule's {iters} iterations"}), flush=True)
+        sys.exit(2)
     X_np, labels = synth.make_points(w)
     Y0_np = synth.make_init(w)
     X = torch.from_numpy(X_np).to(dev)
     Y0 = torch.from_numpy(Y0_np).to(dev)
     ws = api.Workspace()
-    ws_grad = api.Workspace()
     stream = torch.cuda.current_stream(dev)
     if args.copy_calibration_mib:
         # reads and writes exactly MiB * 2^20 bytes each (the MulFunctor elementwise kernel)
@@ -135,57 +158,112 @@ def main():
 
     ws_opt = api.Workspace()
 
-    def one_step(events):
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def affinity_stage():
+        """kNN, calibration, symmetrisation (one host sync to read nnz)."""
+        t = [ev() for _ in range(4)]
+        t[0].record(stream)
         idx, d2 = api.knn(X, w.k, w.knn, n_cand=(w.candidates if w.knn == "bf16" else None), ws=ws)
-        t1.record(stream)
+        t[1].record(stream)
         Pc, beta, conv, nun = api.calibrate_P(d2, w.perplexity)
+        t[2].record(stream)
         P = api.symmetrize(idx, Pc, want_tpos=False, ws=ws)
+        t[3].record(stream)
+        return t, P, idx, d2, Pc
+
+    def new_events(count):
+        # created (recorded once) up front, so none is created in the timed region
+        out = [ev() for _ in range(2 * count)]
+        for e in out:
+            e.record(stream)
+        return out
+
+    if whole:
+        # a step is the whole path: affinities, then every iteration
+        EVERY = 10  # an event pair around every 10th all-pairs launch (events cost ~5 % of a 20k iteration)
+        timed_iters = list(range(0, iters, EVERY))
+
+        def one_step(events):
+            t, P, idx, d2, Pc = affinity_stage()
+            st = tsne.State.start(Y0)
+            t4, t5 = ev(), ev()
+            t4.record(stream)
+            api.optimize(st.Y, st.update, st.gains, P, 0, iters, w.lr, w.exaggeration, w.exaggeration_iters,
+                         w.momentum_early, w.momentum_late, events=events, ws=ws_opt)
+            t5.record(stream)
+            return (t[0], t[1], t[3], t4, t5), P, idx, d2, Pc
+
+        for _ in range(args.warmup):
+            one_step(None)
+        torch.cuda.synchronize()
+        progress(f"{args.warmup} warmup step(s) done")
+        evs_all = []
+        for _ in range(args.steps):
+            evs = [None] * (2 * iters)
+            pairs = new_events(len(timed_iters))
+            for q, i in enumerate(timed_iters):
+                evs[2 * i], evs[2 * i + 1] = pairs[2 * q], pairs[2 * q + 1]
+            evs_all.append(evs)
+        marks = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for s_ in range(args.steps):
+            m, P, idx, d2, Pc = one_step(evs_all[s_])
+            marks.append(m)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        grad_ms = np.array([evs_all[s_][2 * i].elapsed_time(evs_all[s_][2 * i + 1])
+                            for s_ in range(args.steps) for i in timed_iters])
+        knn_s = float(np.median([m[0].elapsed_time(m[1]) for m in marks])) / 1e3
+        aff_s = float(np.median([m[0].elapsed_time(m[2]) for m in marks])) / 1e3
+        iter_ms = float(np.median([m[3].elapsed_time(m[4]) for m in marks])) / iters
+        iters_per_step = iters
+        step_desc = "the whole path: kNN, calibration, symmetrisation and all iterations"
+    else:
+        # the one-off affinity stage, timed once after one untimed run
+        affinity_stage()
+        torch.cuda.synchronize()
+        reps = []
+        for _ in range(3):
+            t, P, idx, d2, Pc = affinity_stage()
+            torch.cuda.synchronize()
+            reps.append((t[0].elapsed_time(t[1]), t[1].elapsed_time(t[2]), t[2].elapsed_time(t[3])))
+        knn_s, cal_ms, sym_ms = (float(np.median([r[q] for r in reps])) for q in range(3))
+        knn_s /= 1e3
+        aff_s = knn_s + (cal_ms + sym_ms) / 1e3
+        progress(f"affinity stage: kNN {knn_s:.3f} s, calibration {cal_ms:.2f} ms, symmetrisation {sym_ms:.2f} ms")
         st = tsne.State.start(Y0)
-        t2 = torch.cuda.Event(enable_timing=True)
-        t3 = torch.cuda.Event(enable_timing=True)
-        t2.record(stream)
-        api.optimize(st.Y, st.update, st.gains, P, 0, iters, w.lr, w.exaggeration, w.exaggeration_iters,
-                     w.momentum_early, w.momentum_late, events=events, ws=ws_opt)
-        t3.record(stream)
-        return (t0, t1, t2, t3), st, P, idx, d2, Pc
 
-    for _ in range(args.warmup):
-        one_step(None)
-    torch.cuda.synchronize()
-    progress(f"{args.warmup} warmup step(s) done")
+        def one_step(events):
+            t0_ = st.t
+            api.optimize(st.Y, st.update, st.gains, P, t0_, t0_ + sl, w.lr, w.exaggeration, w.exaggeration_iters,
+                         w.momentum_early, w.momentum_late, events=events, ws=ws_opt)
+            st.t = t0_ + sl
 
-    # an event pair around every EVERY-th launch of the all-pairs kernel in
-    # each timed step (events on every launch cost ~5 % of an iteration at
-    # 20k points); created (recorded once) up front
-    EVERY = 10
-    timed_iters = list(range(0, iters, EVERY))
-    ev = []
-    for _ in range(args.steps):
-        evs = [None] * (2 * iters)
-        for i in timed_iters:
-            evs[2 * i] = torch.cuda.Event(enable_timing=True)
-            evs[2 * i + 1] = torch.cuda.Event(enable_timing=True)
-            evs[2 * i].record(stream)
-            evs[2 * i + 1].record(stream)
-        ev.append(evs)
-    knn_ev = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        kev, st, P, idx, d2, Pc = one_step(ev[s])
-        knn_ev.append(kev)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+        for _ in range(args.warmup):
+            one_step(None)
+        torch.cuda.synchronize()
+        progress(f"{args.warmup} warmup step(s) of {sl} iterations done (t = {st.t})")
+        evs_all = [new_events(sl) for _ in range(args.steps)]
+        t_first = st.t
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for s_ in range(args.steps):
+            one_step(evs_all[s_])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        grad_ms = np.array([e[2 * i].elapsed_time(e[2 * i + 1]) for e in evs_all for i in range(sl)])
+        iter_ms = elapsed * 1e3 / (args.steps * sl)
+        iters_per_step = sl
+        step_desc = (f"{sl} consecutive iterations of the {iters}-iteration schedule (gradient + step, "
+                     f"tsne_optimize); timed steps ran t = {t_first}..{st.t - 1}; the one-off affinity stage "
+                     f"(kNN, calibration, symmetrisation) is timed separately in affinity_s")
     progress(f"{args.steps} timed step(s): {elapsed:.3f} s")
 
-    pairs_per_step = float(n) * float(n - 1) * iters
+    pairs_per_step = float(n) * float(n - 1) * iters_per_step
     value = pairs_per_step * args.steps / elapsed
-    grad_ms = np.array([ev[s][2 * i].elapsed_time(ev[s][2 * i + 1]) for s in range(args.steps) for i in timed_iters])
-    knn_fp32_s = float(np.median([e[0].elapsed_time(e[1]) for e in knn_ev])) / 1e3
-    iter_ms = float(np.median([e[2].elapsed_time(e[3]) for e in knn_ev])) / iters
     grad_ms_mean = float(grad_ms.mean())
     flops_per_call = api.KLGRAD_FLOPS_PER_ORDERED_PAIR * float(n) * float(n - 1)
     achieved_tflops = flops_per_call / (grad_ms_mean * 1e-3) / 1e12
@@ -205,58 +283,75 @@ def main():
 
     # --- BF16-MFMA vs FP32 kNN build, outside the timed region -------------
     phase("knn_compare")
-    knn_cmp = {}
-    ncmp = args.knn_compare_n
-    if ncmp:
-        Xc_np, _ = synth.make_points("c3", n=ncmp)
-        Xc = torch.from_numpy(Xc_np).to(dev)
-        wsk = api.Workspace()
 
+    def p_diff(PA, PB, nn):
+        """L1 of PA - PB over the union pattern and the largest relative
+        difference over common entries (on the device)."""
+        def keys(P):
+            rows = torch.repeat_interleave(torch.arange(nn, device=dev), P.row_ptr[1:] - P.row_ptr[:-1])
+            return rows * nn + P.col.long()
+        ka, kb = keys(PA), keys(PB)
+        kk = torch.cat([ka, kb])
+        vv = torch.cat([PA.val.double(), -PB.val.double()])
+        uk, inv = torch.unique(kk, return_inverse=True)
+        acc = torch.zeros(uk.numel(), dtype=torch.float64, device=dev).index_add_(0, inv, vv)
+        cnt = torch.zeros(uk.numel(), dtype=torch.int32, device=dev).index_add_(
+            0, inv, torch.ones_like(inv, dtype=torch.int32))
+        l1 = float(acc.abs().sum())
+        va = torch.zeros(uk.numel(), dtype=torch.float64, device=dev).index_add_(0, inv[:ka.numel()],
+                                                                               PA.val.double())
+        common = cnt == 2
+        rel = float((acc[common].abs() / va[common]).max()) if bool(common.any()) else 0.0
+        return l1, rel
+
+    def knn_compare(Xc, nn, reps32, reps16, wsk, label):
         def time_knn(prec, reps):
             out = None
             ts = []
             for r in range(reps + 1):
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record(stream)
+                a_, b_ = ev(), ev()
+                a_.record(stream)
                 out = api.knn(Xc, 90, prec, n_cand=(180 if prec == "bf16" else None), ws=wsk)
-                b.record(stream)
+                b_.record(stream)
                 torch.cuda.synchronize()
                 if r > 0:
-                    ts.append(a.elapsed_time(b) / 1e3)
+                    ts.append(a_.elapsed_time(b_) / 1e3)
             return float(np.median(ts)), out
 
-        t32, (i32, d32) = time_knn("fp32", 3)
-        t16, (i16, d16) = time_knn("bf16", 5)
-        a32 = i32.cpu().numpy()
-        a16 = i16.cpu().numpy()
-        same = np.mean([len(set(p) & set(q)) / 90 for p, q in zip(a16.tolist(), a32.tolist())])
-        # P built from each neighbour graph (same calibration and symmetrisation kernels)
-        import scipy.sparse as sp
+        t32, (i32, d32) = time_knn("fp32", reps32)
+        t16, (i16, d16) = time_knn("bf16", reps16)
+        a32 = torch.sort(i32.long(), 1).values
+        a16 = torch.sort(i16.long(), 1).values
+        hits = 0
+        for r0 in range(0, nn, 100_000):
+            pos = torch.searchsorted(a32[r0:r0 + 100_000], a16[r0:r0 + 100_000]).clamp(max=89)
+            hits += int((torch.gather(a32[r0:r0 + 100_000], 1, pos) == a16[r0:r0 + 100_000]).sum())
+        same_rows = (a16 == a32).all(1)
+        P32 = api.symmetrize(i32, api.calibrate_P(d32, 30.0)[0], want_tpos=False, ws=wsk)
+        P16 = api.symmetrize(i16, api.calibrate_P(d16, 30.0)[0], want_tpos=False, ws=wsk)
+        l1, prel = p_diff(P16, P32, nn)
+        dsame = None
+        if bool(same_rows.any()):
+            d32s, d16s = d32[same_rows].double(), d16[same_rows].double()
+            dsame = float(((d16s - d32s).abs() / d32s.clamp(min=1e-30)).max())
+        mfma_flops = 2.0 * nn * nn * 64
+        progress(f"kNN comparison at n={nn} done")
+        return {"n": nn, "workload": label, "k": 90, "n_cand": 180, "fp32_exact_s": t32, "bf16_mfma_rerank_s": t16,
+                "speedup": t32 / t16, "bf16_vs_fp32_set_agreement": hits / (nn * 90.0),
+                "bf16_vs_fp32_rows_identical": float(same_rows.double().mean()),
+                "bf16_vs_fp32_d2_max_rel_identical_rows": dsame,
+                "bf16_vs_fp32_P_L1": l1, "bf16_vs_fp32_P_max_rel_common": prel,
+                "bf16_mfma_tflops_executed": mfma_flops / t16 / 1e12}
 
-        def p_of(i, d):
-            S = api.symmetrize(i, api.calibrate_P(d, 30.0)[0], want_tpos=False, ws=wsk)
-            return sp.csr_matrix((S.val.cpu().numpy().astype(np.float64), S.col.cpu().numpy(),
-                                  S.row_ptr.cpu().numpy()), shape=(ncmp, ncmp))
-
-        P32, P16 = p_of(i32, d32), p_of(i16, d16)
-        diff = abs(P16 - P32)
-        both = P32.multiply(P16 != 0).tocsr()
-        rel = abs(both - P16.multiply(P32 != 0)).multiply(both.power(-1)).tocsr() if both.nnz else both
-        rows_same = np.flatnonzero((np.sort(a16, 1) == np.sort(a32, 1)).all(1))
-        dsl = d32.cpu().numpy()[rows_same].astype(np.float64)
-        d16s = d16.cpu().numpy()[rows_same].astype(np.float64)
-        mfma_flops = 2.0 * ncmp * ncmp * 64
-        knn_cmp = {"n": ncmp, "k": 90, "n_cand": 180, "fp32_exact_s": t32, "bf16_mfma_rerank_s": t16,
-                   "speedup": t32 / t16, "bf16_vs_fp32_set_agreement": float(same),
-                   "bf16_vs_fp32_rows_identical": float(rows_same.size / ncmp),
-                   "bf16_vs_fp32_d2_max_rel_identical_rows": float(
-                       np.max(np.abs(d16s - dsl) / np.maximum(dsl, 1e-30))) if rows_same.size else None,
-                   "bf16_vs_fp32_P_L1": float(diff.sum()),
-                   "bf16_vs_fp32_P_max_rel_common": float(rel.max()) if rel.nnz else 0.0,
-                   "bf16_mfma_tflops_executed": mfma_flops / t16 / 1e12}
-        del Xc, i32, d32, i16, d16, P32, P16, diff, both, rel
-        progress(f"kNN comparison at n={ncmp} done")
+    knn_cmp = {"in_workload_s": knn_s, "precision": w.knn}
+    if w.knn == "bf16" and args.knn_fp32_same_n:
+        knn_cmp.update(knn_compare(X, n, 1, 3, ws, f"{w.name} (the benchmark's own points)"))
+    ncmp = args.knn_compare_n
+    if ncmp:
+        Xc_np, _ = synth.make_points("c3", n=ncmp)
+        Xc = torch.from_numpy(Xc_np).to(dev)
+        knn_cmp["c3_shape"] = knn_compare(Xc, ncmp, 3, 5, api.Workspace(), "c3 shape (30 equal clusters)")
+        del Xc
 
     phase("autograd")
     # --- differentiation form (KL autograd) at the 50k-point shape ----------
@@ -426,7 +521,7 @@ def main():
 
         thr = oracle.num_threads()
         big = n > 100_000
-        qrows = (np.random.default_rng(7).choice(n, 200, replace=False).astype(np.int64) if big
+        qrows = (np.random.default_rng(7).choice(n, 1000, replace=False).astype(np.int64) if big
                  else np.arange(0, n, 10, dtype=np.int64))
         t0 = time.perf_counter()
         oi, od = oracle.knn(X_np, w.k, rows=qrows)
@@ -441,11 +536,12 @@ def main():
         if big:
             # the full FP64 gradient is O(n^2) per iteration: time per-row parts
             # (Z_i, repulsion, attraction; O(n) each) on sampled rows and scale
-            grows = np.random.default_rng(8).choice(n, 64, replace=False).astype(np.int64)
+            grows = np.random.default_rng(8).choice(n, 256, replace=False).astype(np.int64)
             t0 = time.perf_counter()
             oracle.grad_rows(Y, grows, Sg)
             t_it = (time.perf_counter() - t0) * (n / grows.size)
-            it_desc = f"per-row gradient parts on {grows.size} of {n} rows (time x{n // grows.size}) per iteration"
+            it_desc = (f"per-row gradient parts (Z_i, repulsion, attraction) on {grows.size} of {n} rows (time "
+                       f"x{n // grows.size}) per iteration")
         else:
             U = np.zeros_like(Y)
             G = np.ones_like(Y)
@@ -457,13 +553,16 @@ def main():
                 oracle.step(Y, U, G, g, w.lr, m)
             t_it = (time.perf_counter() - t0) / args.cpu_iters
             it_desc = f"{args.cpu_iters} of {iters} gradient+step iterations (time x{iters / args.cpu_iters:g})"
-        t_total = t_knn + t_ps + t_it * iters
+        t_run = t_knn + t_ps + t_it * iters
+        t_step = t_run if whole else t_it * iters_per_step
         progress("CPU baseline timed")
-        cpu = {"value": pairs_per_step / t_total, "unit": "pair interactions/s", "cores": thr, "kind": "oracle",
+        cpu = {"value": pairs_per_step / t_step, "unit": "pair interactions/s", "cores": thr, "kind": "oracle",
                "sample": (f"FP64 oracle, {thr} threads: exact kNN on {qrows.size} of {n} query rows (time x"
                           f"{n / qrows.size:g}); calibration + symmetrisation of a full-size seeded k={w.k} graph; "
-                          f"{it_desc}; host {platform.processor() or platform.machine()}"),
-               "s_per_step_extrapolated": t_total}
+                          f"{it_desc}; host {platform.processor() or platform.machine()}; value = the step's "
+                          f"pair interactions / the oracle's extrapolated time for the same step "
+                          f"({'the whole path' if whole else f'{iters_per_step} iterations'})"),
+               "s_per_step_extrapolated": t_step, "s_per_run_extrapolated": t_run}
         # the oracles of the widened rows beside their GPU legs (bounded
         # samples, seeded synthetic inputs of the same recipes)
         nxt = {}
@@ -518,15 +617,32 @@ def main():
             np.max(np.abs(ddq[same] - od[same]) / np.maximum(od[same], 1e-30)))
         Pd = api.SparseP(torch.from_numpy(Sg.row_ptr).to(dev), torch.from_numpy(Sg.col).to(dev),
                          torch.from_numpy(Sg.val.astype(np.float32)).to(dev), None, n)
-        for ystd, a in (((0.01, 12.0), (20.0, 1.0)) if not big else ()):
+        for ystd, a in ((0.01, 12.0), (20.0, 1.0)):
             Yt = synth.random_embedding(n, ystd, 99)
-            gg, Zg, klg, _ = api.kl_grad(torch.from_numpy(Yt).to(dev), Pd, a, want_Z=True, want_kl=True)
-            go, Zo, klo = oracle.kl_grad(Yt.astype(np.float64), Sg, a)
-            gg = gg.cpu().numpy().astype(np.float64)
-            errors[f"grad_rel_norm_ystd{ystd:g}"] = float(np.linalg.norm(gg - go) / np.linalg.norm(go))
-            errors[f"grad_max_entry_rel_ystd{ystd:g}"] = float(np.abs(gg - go).max() / np.abs(go).max())
-            errors[f"Z_rel_ystd{ystd:g}"] = abs(Zg.item() - Zo) / Zo
-            errors[f"KL_rel_ystd{ystd:g}"] = abs(klg.item() - klo) / abs(klo)
+            if big:
+                # sampled rows: the oracle's per-row parts with the GPU's Z,
+                # which is checked through its per-row sums on the same rows
+                gg, Zg, _, Zr = api.kl_grad(torch.from_numpy(Yt).to(dev), Pd, a, want_Z=True, want_Zrow=True)
+                er = np.random.default_rng(9).choice(n, 256, replace=False).astype(np.int64)
+                Zo_r, Ro, Ao = oracle.grad_rows(Yt.astype(np.float64), er, Sg)
+                go = 4.0 * (a * Ao - Ro / Zg.item())
+                gg = gg.cpu().numpy().astype(np.float64)[er]
+                errors[f"Zrow_rel_max_ystd{ystd:g}_sampled"] = float(
+                    np.max(np.abs(Zr.cpu().numpy()[er] - Zo_r) / Zo_r))
+                errors[f"Z_sum_of_rows_rel_ystd{ystd:g}"] = abs(float(Zr.sum()) - Zg.item()) / Zg.item()
+                tag = "_sampled"
+            else:
+                gg, Zg, klg, _ = api.kl_grad(torch.from_numpy(Yt).to(dev), Pd, a, want_Z=True, want_kl=True)
+                go, Zo, klo = oracle.kl_grad(Yt.astype(np.float64), Sg, a)
+                gg = gg.cpu().numpy().astype(np.float64)
+                errors[f"Z_rel_ystd{ystd:g}"] = abs(Zg.item() - Zo) / Zo
+                errors[f"KL_rel_ystd{ystd:g}"] = abs(klg.item() - klo) / abs(klo)
+                tag = ""
+            errors[f"grad_rel_norm_ystd{ystd:g}{tag}"] = float(np.linalg.norm(gg - go) / np.linalg.norm(go))
+            errors[f"grad_max_entry_rel_ystd{ystd:g}{tag}"] = float(np.abs(gg - go).max() / np.abs(go).max())
+        errors["sample"] = ("kNN: the GPU lists of the benchmark's own run on the oracle's sampled query rows; "
+                            "gradient: the oracle's P of a seeded random k-regular graph, seeded embeddings"
+                            + ("; 256 sampled rows against the oracle's per-row parts" if big else ""))
 
     telemetry = None
     if mon is not None:
@@ -557,13 +673,19 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: exact t-SNE, N={n} x {w.d}, {w.clusters}-cluster mixture "
-                               f"({w.weights} weights), perplexity {w.perplexity:g}, k={w.k}, {w.knn} kNN, "
-                               f"{iters} iterations",
-                   "n": n, "d": w.d, "k": w.k, "perplexity": w.perplexity, "iters": iters, "knn": w.knn},
+                               f"({w.weights} weights{', PCA-like spectrum' if w.shape == 'pca' else ''}), "
+                               f"perplexity {w.perplexity:g}, k={w.k}, {w.knn} kNN"
+                               f"{f' (n_cand {w.candidates})' if w.knn == 'bf16' else ''}, {iters} iterations",
+                   "n": n, "d": w.d, "k": w.k, "perplexity": w.perplexity, "iters": iters, "knn": w.knn,
+                   "step": step_desc, "iterations_per_step": iters_per_step},
         "repulsion_pairs_per_s": float(n) * (n - 1) / (grad_ms_mean * 1e-3),
         "iteration_ms": iter_ms,
         "iteration_pairs_per_s": float(n) * (n - 1) / (iter_ms * 1e-3),
-        "knn_build_s": {f"{w.knn}_in_step": knn_fp32_s, **knn_cmp},
+        "affinity_s": aff_s,
+        "run_s_estimate": {"value": aff_s + iters * iter_ms / 1e3,
+                           "what": f"the whole {iters}-iteration run: the measured affinity stage plus {iters} x "
+                                   f"the measured per-iteration time"},
+        "knn_build_s": knn_cmp,
         "kl_autograd": diff,
         "interpolated_gradient": interp,
         "pca": pca,

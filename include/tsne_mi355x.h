@@ -135,8 +135,12 @@ int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t precision,
  * exponentials; a few 1e-7 at k = 90 against an FP64 evaluation), so the
  * entropy at the returned beta, evaluated in FP64 from the same FP32
  * distances, is within tol.
- * Rows that do not reach it in max_iter evaluations (e.g. all k distances
- * equal) keep the last beta and get converged = 0.
+ * Rows that do not reach it in max_iter evaluations keep the last beta and
+ * get converged = 0.  A row whose smallest distance is shared by more than
+ * `perplexity` neighbours (e.g. all k distances equal) has H > ln(perplexity)
+ * for every beta: its expansion stops at beta = 2^126, where P_cond is the
+ * limit, uniform over those tied neighbours (0 elsewhere unless a gap
+ * s_j is below about 1e-36).
  *
  *   nbr_d2     [n][k] float, read-only (any order within a row).
  *   perplexity 0 < perplexity < k.   tol > 0.   max_iter >= 1.

@@ -51,6 +51,8 @@ def lib():
                                      C.c_void_p]
         L.oracle_grad_rows.argtypes = [_f64p, C.c_int64, _i64p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_grad_rows_scale.argtypes = [_f64p, C.c_int64, _i64p, C.c_int64, C.c_void_p, C.c_void_p,
+                                             C.c_void_p, _f64p, _f64p]
         L.oracle_kl.argtypes = [_f64p, C.c_int64, _i64p, _i32p, _f64p, C.c_void_p, C.c_void_p]
         L.oracle_kl_backward.argtypes = [_f64p, C.c_int64, _i64p, _i32p, _f64p, C.c_double, C.c_void_p, C.c_void_p]
         L.oracle_step.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_int64, C.c_double, C.c_double, C.c_double,
@@ -186,6 +188,23 @@ def grad_rows(Y, rows, P: CSR | None = None):
     _check(lib().oracle_grad_rows(Y, Y.shape[0], rows, m, _opt(rp), _opt(cl), _opt(vl), _opt(Zr), _opt(Rr),
                                   _opt(Ar)), "grad_rows")
     return Zr, Rr, Ar
+
+
+def grad_rows_scale(Y, rows, P: CSR | None = None):
+    """Per-row, per-coordinate term magnitudes (Rabs, Aabs), float64 [m, 2]:
+    sum_j w^2 |y_i - y_j| and sum_row |p| w |y_i - y_j|, the scale of the
+    rounding error of R_i and A_i in any summation order."""
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    m = rows.shape[0]
+    Ra = np.empty((m, 2))
+    Aa = np.empty((m, 2))
+    rp = None if P is None else P.row_ptr
+    cl = None if P is None else P.col
+    vl = None if P is None else P.val
+    _check(lib().oracle_grad_rows_scale(Y, Y.shape[0], rows, m, _opt(rp), _opt(cl), _opt(vl), Ra, Aa),
+           "grad_rows_scale")
+    return Ra, Aa
 
 
 def kl(Y, P: CSR):

@@ -432,6 +432,43 @@ int oracle_grad_rows(const double* Y, int64_t n, const int64_t* rows, int64_t n_
   return bad ? -1 : 0;
 }
 
+/* Per-row, per-coordinate magnitude of the terms that make up the parts
+ * above (the scale of their rounding error in any summation order), for
+ * i = rows[r] and coordinate c in {x, y}:
+ *   Rabs[r][c] = sum_{j != i} w_ij^2 |y_ic - y_jc|,
+ *   Aabs[r][c] = sum_{e in row i} |p_e| w_e |y_ic - y_col(e),c|.
+ * |R_i,c| <= Rabs[r][c] and |A_i,c| <= Aabs[r][c], with equality when every
+ * term has the same sign. */
+int oracle_grad_rows_scale(const double* Y, int64_t n, const int64_t* rows, int64_t n_rows, const int64_t* row_ptr,
+                           const int32_t* col, const double* val, double* Rabs, double* Aabs) {
+  if (!Y || n < 2 || !rows || n_rows < 0 || !Rabs || !Aabs) return -1;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t r = 0; r < n_rows; ++r) {
+    int64_t i = rows[r];
+    if (i < 0 || i >= n) { bad = 1; continue; }
+    double rx = 0.0, ry = 0.0, ax = 0.0, ay = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double w = w_of(Y, i, j);
+      rx += w * w * fabs(Y[2 * i] - Y[2 * j]);
+      ry += w * w * fabs(Y[2 * i + 1] - Y[2 * j + 1]);
+    }
+    if (row_ptr && col && val)
+      for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        int64_t j = col[e];
+        double pw = fabs(val[e]) * w_of(Y, i, j);
+        ax += pw * fabs(Y[2 * i] - Y[2 * j]);
+        ay += pw * fabs(Y[2 * i + 1] - Y[2 * j + 1]);
+      }
+    Rabs[2 * r] = rx;
+    Rabs[2 * r + 1] = ry;
+    Aabs[2 * r] = ax;
+    Aabs[2 * r + 1] = ay;
+  }
+  return bad ? -1 : 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* KL(P||Q) as a function of Y and of the stored values p_e, for the
  * differentiation form.  P need not be symmetric nor sum to one:

@@ -8,6 +8,10 @@
 
 namespace tsne {
 
+// Largest beta the bracket expansion reaches (a power of two, so the
+// doubling stays exact; far below FLT_MAX).
+constexpr float CALIB_BETA_MAX = 0x1p126f;
+
 template <int KPL>
 __global__ __launch_bounds__(256) void calibrate_kernel(const float* __restrict__ d2, int64_t n, int k, float Hstar,
                                                         float tol, int max_iter, float* __restrict__ P,
@@ -53,7 +57,17 @@ __global__ __launch_bounds__(256) void calibrate_kernel(const float* __restrict_
     if (it == max_iter - 1) break;
     if (H > Hstar) {
       lo = beta;
-      beta = isinf(hi) ? beta * 2.0f : 0.5f * (beta + hi);
+      if (isinf(hi)) {
+        // Not bracketed yet.  A row whose nearest distance is shared by
+        // more than `perplexity` neighbours keeps H above the target for
+        // every beta (its limit is uniform over those ties): stop at the
+        // cap, where every positive s of a normal size already gives
+        // e = 0, instead of doubling beta to infinity (-inf * 0 = NaN).
+        if (beta >= CALIB_BETA_MAX) break;
+        beta *= 2.0f;
+      } else {
+        beta = 0.5f * (beta + hi);
+      }
     } else {
       hi = beta;
       beta = 0.5f * (lo + beta);

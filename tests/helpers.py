@@ -98,3 +98,96 @@ def check_knn(X, rows, g_idx, g_d2, o_idx, o_d2, tie=NEAR_TIE, min_agree=1.0, d2
     adj = tie_ok / (m * k)
     assert adj >= min_agree, (raw, adj)
     return raw, adj
+
+
+# Per-entry bound of the gradient's rounding error, relative to the row's
+# term magnitudes 4 (alpha sum |p w (y_i - y_j)| + sum w^2 |y_i - y_j| / Z)
+# per coordinate: FP32 terms of a few ulps each, summed in FP32 over at most
+# a few hundred terms before FP64.  A row that lost one superblock's
+# contribution would be off by about 1/ns of that scale.
+ROW_RTOL = 5e-5
+
+
+def check_grad_rows(g, go, Y64, rows, S, alpha, Z, rtol=ROW_RTOL):
+    """Per row and coordinate: |g - g_ref| <= rtol * the row's term magnitude.
+    g, go: [m, 2] for the m query rows; S: the oracle CSR the oracle used.
+    Returns the largest error relative to that scale."""
+    Ra, Aa = oracle.grad_rows_scale(Y64, rows, S)
+    scale = 4.0 * (alpha * Aa + Ra / Z)
+    err = np.abs(np.asarray(g, np.float64) - np.asarray(go, np.float64))
+    ratio = err / np.maximum(scale, 1e-300)
+    worst = int(np.argmax(ratio.max(1)))
+    assert ratio.max() <= rtol, (f"row {int(rows[worst])}: |dg| {err[worst]} vs term scale {scale[worst]} "
+                                 f"(ratio {ratio.max():.3g})")
+    return float(ratio.max())
+
+
+def torch_knn_graph(X, k, dev, chunk=2048, extra=10):
+    """Neighbour lists of every row of X (float32 [n, d]) built with plain
+    torch on the device: candidates from the expanded-form FP32 distance
+    matrix (k + extra per row), then FP32 direct-difference distances of the
+    candidates, ordered by (d, j), the k best kept, self excluded.
+
+    A test input builder only: it gives full-size lists with the real
+    neighbour structure (hubs, in-degree spread) of a point cloud for the
+    stages after the kNN, at sizes where the oracle's exact kNN of every row
+    would take hours.  It is neither the oracle nor the library under test;
+    both sides of a parity check then take the same lists.  Returns
+    (idx int32 [n, k], d2 float32 [n, k]) as NumPy arrays.
+    """
+    Xt = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(dev)
+    n = Xt.shape[0]
+    XT = Xt.t().contiguous()
+    sq = (Xt * Xt).sum(1)
+    m = k + extra
+    idx_out = torch.empty((n, k), dtype=torch.int32, device=dev)
+    d2_out = torch.empty((n, k), dtype=torch.float32, device=dev)
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        D = torch.mm(Xt[r0:r1], XT)
+        D.mul_(-2.0).add_(sq[r0:r1, None]).add_(sq[None, :])
+        rr = torch.arange(r0, r1, device=dev)
+        D[rr - r0, rr] = float("inf")
+        cand = torch.topk(D, m, dim=1, largest=False).indices
+        del D
+        diff = Xt[r0:r1, None, :] - Xt[cand]
+        dc = (diff * diff).sum(-1)
+        # (d, j) order: sort by j, then a stable sort by d
+        cj, oj = torch.sort(cand, dim=1)
+        dj = torch.gather(dc, 1, oj)
+        dd, od = torch.sort(dj, dim=1, stable=True)
+        jj = torch.gather(cj, 1, od)
+        idx_out[r0:r1] = jj[:, :k].to(torch.int32)
+        d2_out[r0:r1] = dd[:, :k]
+    return idx_out.cpu().numpy(), d2_out.cpu().numpy()
+
+
+EPS32 = 2.0 ** -24
+
+
+def check_step_rows(Yn, Un, Gn, Y, U, G, g_ref, tol_g, lr, mom, inc=0.2, dec=0.8, mn=0.01):
+    """One optimiser step of the GPU (Yn, Un, Gn, float32) against the oracle's
+    step from the same state (Y, U, G, exact in float64) with the reference
+    gradient g_ref, whose error bound per coordinate is tol_g.
+
+    The gains rule branches on sign(g u): where |g_ref| <= tol_g the GPU's
+    FP32 gradient may have the other sign, so there Gn must be one of the two
+    branches; elsewhere it must be the oracle's.  The update must equal
+    mom U - lr Gn g_ref within lr Gn tol_g plus FP32 rounding, and Yn must be
+    the FP32 sum Y + Un.  Returns the number of ambiguous coordinates."""
+    Y, U, G, g_ref = (np.asarray(a, np.float64) for a in (Y, U, G, g_ref))
+    Yn, Un, Gn = (np.asarray(a, np.float64) for a in (Yn, Un, Gn))
+    Yo, Uo, Go = Y.copy(), U.copy(), G.copy()
+    oracle.step(Yo, Uo, Go, g_ref, lr, mom, inc, dec, mn)
+    amb = np.abs(g_ref) <= tol_g
+    gain_rtol = 4 * EPS32
+    assert np.all(np.abs(Gn - Go)[~amb] <= gain_rtol * Go[~amb]), "gains branch differs from the oracle's"
+    up, down = np.maximum(G + inc, mn), np.maximum(G * dec, mn)
+    either = (np.abs(Gn - up) <= gain_rtol * up) | (np.abs(Gn - down) <= gain_rtol * down)
+    assert np.all(either[amb])
+    Ue = mom * U - lr * Gn * g_ref
+    bound = lr * Gn * tol_g + 4 * EPS32 * (np.abs(mom * U) + lr * Gn * np.abs(g_ref)) + 1e-30
+    bad = np.abs(Un - Ue) > bound
+    assert not bad.any(), (np.argwhere(bad)[:3], Un[bad][:3], Ue[bad][:3], bound[bad][:3])
+    assert np.all(np.abs(Yn - (Y + Un)) <= EPS32 * np.abs(Y + Un) + 1e-30)
+    return int(amb.sum())

@@ -8,7 +8,8 @@ import pytest
 import torch
 
 import oracle
-from helpers import oracle_problem, random_graph_P, rel, say, sparse_to_dev, to_dev
+from helpers import (ROW_RTOL, check_grad_rows, check_step_rows, oracle_problem, random_graph_P, rel, say,
+                     sparse_to_dev, to_dev)
 from paper_2605_13928_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -29,6 +30,9 @@ def compare(dev, S, Y32, alpha, zrow=True):
     go, Zo, klo = oracle.kl_grad(Y32.astype(np.float64), So, alpha)
     e = rel(g, go)
     assert e <= GRAD_RTOL, e
+    # and row by row, so that one wrong row cannot hide in the norm
+    n = Y32.shape[0]
+    check_grad_rows(g, go, Y32.astype(np.float64), np.arange(n), So, alpha, Zo)
     assert abs(Z.item() - Zo) <= 1e-6 * Zo
     assert abs(kl.item() - klo) <= 1e-5 * max(1.0, abs(klo))
     assert np.abs(g.sum(0)).max() <= 1e-5 * np.abs(g).sum()
@@ -102,6 +106,7 @@ def test_klgrad_sampled_rows(dev, n):
     go = 4.0 * (Ao - Ro / Zg)
     e = rel(g.cpu().numpy()[rows], go)
     assert e <= GRAD_RTOL, e
+    check_grad_rows(g.cpu().numpy()[rows], go, Y.astype(np.float64), rows, So, 1.0, Zg)
 
 
 def test_fused_attraction_full_scale(dev):
@@ -140,6 +145,8 @@ def fused_first_iteration(dev, n, seed):
     go = 4.0 * (12.0 * Ao - Ro / Z.item())
     e = rel(g[rows], go)
     assert e <= GRAD_RTOL, e
+    # g is recovered from the update, which adds one FP32 rounding of lr 0.8 g
+    check_grad_rows(g[rows], go, Y.astype(np.float64), rows, So, 12.0, Z.item())
     # and the step itself: Y + update
     np.testing.assert_array_equal(Yo.cpu().numpy(), (Yd + U).cpu().numpy())
 
@@ -163,3 +170,38 @@ def test_fused_loop_bitwise_reproducible_c2(dev):
         runs.append((Y.cpu(), U.cpu(), G.cpu()))
     for a, b in zip(runs[0], runs[1]):
         assert torch.equal(a, b)
+
+
+def late_state(n, seed):
+    """A mid-run optimiser state: embedding at the late scale, a non-zero
+    update and gains spread over [0.01, 3] (seeded draws, float32)."""
+    rng = np.random.default_rng(seed)
+    Y = synth.random_embedding(n, 15.0, seed)
+    U = (rng.standard_normal((n, 2)) * 0.3).astype(np.float32)
+    G = rng.uniform(0.01, 3.0, (n, 2)).astype(np.float32)
+    G[rng.random((n, 2)) < 0.05] = 0.01  # at the floor
+    return Y, U, G
+
+
+@pytest.mark.parametrize("t", [99, 100, 150])
+def test_fused_loop_late_schedule_c2(dev, t):
+    # One tsne_optimize iteration at t (99: the last exaggerated one; 100:
+    # alpha = 1 and momentum 0.8 from here on; 150: mid-run) from a state
+    # with a non-zero update and gains != 1, against oracle.kl_grad +
+    # oracle.step at the same state, every row and coordinate.
+    say("fused loop late schedule", t)
+    n = 20_000
+    idx, d2, Pc, S = random_graph_P(n, 90, 30.0, 2)
+    So = widen(S, S.val.astype(np.float32))
+    P = sparse_to_dev(So, dev)
+    Y, U, G = late_state(n, 700 + t)
+    Yd, Ud, Gd = to_dev(Y, dev), to_dev(U, dev), to_dev(G, dev)
+    api.optimize(Yd, Ud, Gd, P, t, t + 1, lr=200.0, exaggeration=12.0, exaggeration_iters=100,
+                 momentum_early=0.5, momentum_late=0.8)
+    alpha, mom = oracle.tsne_schedule(t)
+    Y64 = Y.astype(np.float64)
+    go, Zo, _ = oracle.kl_grad(Y64, So, alpha, want_kl=False)
+    Ra, Aa = oracle.grad_rows_scale(Y64, np.arange(n), So)
+    tol_g = ROW_RTOL * 4.0 * (alpha * Aa + Ra / Zo)
+    amb = check_step_rows(Yd.cpu().numpy(), Ud.cpu().numpy(), Gd.cpu().numpy(), Y, U, G, go, tol_g, 200.0, mom)
+    assert amb <= 2 * n * 1e-3, amb

@@ -83,3 +83,32 @@ def test_calibrate_degenerate_rows(dev):
     assert conv.tolist() == [0, 0, 0, 1, 0, 0, 0, 0, 0, 0]
     assert int(nun.item()) == 9
     np.testing.assert_allclose(P.cpu().numpy()[0], 1.0 / 90, rtol=1e-6)
+
+
+def test_calibrate_unreachable_rows_default_max_iter(dev):
+    # Rows whose nearest distance is shared by more than `perplexity`
+    # neighbours never bracket the target (H > ln 30 for every beta): all 90
+    # distances equal (H = ln 90), and 40 tied minima before 50 larger
+    # distances (H -> ln 40).  At the default 200 evaluations beta must stay
+    # finite and P must be the limit the FP64 oracle reaches: uniform over the
+    # tied neighbours.  Two ordinary rows ride along.
+    say("calibrate unreachable rows, max_iter 200")
+    rng = np.random.default_rng(40)
+    d2 = np.sort(rng.chisquare(50, (6, 90)) * 2.0, axis=1).astype(np.float32)
+    d2[0] = 4.0
+    d2[2, :40] = 1.5
+    d2[2, 40:] = np.linspace(2.0, 30.0, 50)
+    d2[4, :31] = 0.0  # 31 duplicates of the query: one more than the perplexity
+    d2[4, 31:] = np.linspace(0.5, 9.0, 59)
+    d2[5] = rng.permutation(d2[2])  # the tied minima in any order
+    P, beta, conv, nun = api.calibrate_P(to_dev(d2, dev), 30.0)
+    P, beta, conv = P.cpu().numpy(), beta.cpu().numpy(), conv.cpu().numpy()
+    Po, _, convo, _ = oracle.calibrate(d2.astype(np.float64), 30.0, tol=1e-5)
+    assert conv.tolist() == convo.tolist() == [0, 1, 0, 1, 0, 0]
+    assert int(nun.item()) == 4
+    assert np.isfinite(P).all() and np.isfinite(beta).all()
+    np.testing.assert_allclose(P, Po, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(P[0], 1.0 / 90, rtol=1e-6)
+    np.testing.assert_allclose(P[2, :40], 1.0 / 40, rtol=1e-6)
+    assert (P[2, 40:] == 0).all()
+    np.testing.assert_allclose(P[4, :31], 1.0 / 31, rtol=1e-6)

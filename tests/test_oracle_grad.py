@@ -123,3 +123,26 @@ def test_row_parts_compose_gradient(oracle_mod):
     Zr, Rr, Ar = oracle_mod.grad_rows(Y, rows, S)
     assert abs(Zr.sum() - Z) <= 1e-13 * Z
     np.testing.assert_allclose(4 * (12.0 * Ar - Rr / Z), g, rtol=1e-9, atol=1e-12 * np.abs(g).max())
+
+
+def test_row_term_magnitudes(oracle_mod):
+    # The per-row term magnitudes bound the parts they belong to, with
+    # equality where every term has one sign: for the point with the smallest
+    # x every y_i,x - y_j,x is <= 0, for the one with the largest y every
+    # y_i,y - y_j,y >= 0.  A brute-force NumPy evaluation pins the rest.
+    S, Y = make_problem(oracle_mod, 200, 20, 6.0, 5)
+    n = Y.shape[0]
+    rows = np.arange(n)
+    _, R, A = oracle_mod.grad_rows(Y, rows, S)
+    Ra, Aa = oracle_mod.grad_rows_scale(Y, rows, S)
+    assert np.all(np.abs(R) <= Ra * (1 + 1e-12)) and np.all(np.abs(A) <= Aa * (1 + 1e-12))
+    i0, i1 = int(np.argmin(Y[:, 0])), int(np.argmax(Y[:, 1]))
+    assert abs(-R[i0, 0] - Ra[i0, 0]) <= 1e-12 * Ra[i0, 0]
+    assert abs(-A[i0, 0] - Aa[i0, 0]) <= 1e-12 * Aa[i0, 0]
+    assert abs(R[i1, 1] - Ra[i1, 1]) <= 1e-12 * Ra[i1, 1]
+    D = Y[:, None, :] - Y[None, :, :]
+    W = 1.0 / (1.0 + (D ** 2).sum(-1))
+    np.fill_diagonal(W, 0.0)
+    np.testing.assert_allclose(Ra, ((W ** 2)[:, :, None] * np.abs(D)).sum(1), rtol=1e-12)
+    Pd = S.dense()
+    np.testing.assert_allclose(Aa, ((Pd * W)[:, :, None] * np.abs(D)).sum(1), rtol=1e-12)
