@@ -27,7 +27,9 @@ Approximation and Projection for Dimension Reduction", arXiv:1802.03426
   rate alpha0 (1 - t / n_epochs) in epoch t.
 
 Readings of the data-parallel epoch (the published algorithm is sequential
-SGD; these make one epoch a deterministic function of the epoch's start):
+SGD, written out as layout_epoch_sequential; these make one epoch a
+deterministic function of the epoch's start, and the tests check that both
+forms reach the same fuzzy-set cross-entropy and neighbourhood purity):
   - every step of epoch t is evaluated at the positions Y_t and the steps
     are summed: Y_{t+1} = Y_t + sum of steps;
   - schedule: with r_e = w_e / w_max in FP32, stored entry e is sampled in
@@ -230,6 +232,86 @@ def layout(Y0, row_ptr, col, val, n_epochs, a, b, alpha0=1.0, neg_rate=5, seed=0
     for t in range(t0, t1):
         Y = layout_epoch(Y, row_ptr, col, val, t, n_epochs, a, b, alpha0, neg_rate, seed)
     return Y
+
+
+def layout_epoch_sequential(Y, row_ptr, col, val, t, n_epochs, a, b, alpha0=1.0, neg_rate=5, seed=0):
+    """Epoch t of the layout as the published sequential SGD [MHM18] Sec. 3.2:
+    the sampled 1-simplices are visited one after another in storage order,
+    and every step moves the points at once, so a later step sees the
+    positions the earlier ones left.  Per sampled entry (i, j): the
+    attractive step on y_i and its opposite on y_j, then the neg_rate
+    repulsive steps of y_i against uniformly drawn vertices.  Sampling
+    schedule, draws, coefficients and clipping are those of layout_epoch.
+    Plain Python loops: for small graphs only."""
+    Y = np.array(Y, np.float64)
+    n = Y.shape[0]
+    nnz = col.shape[0]
+    alpha = alpha0 * (1.0 - t / n_epochs)
+    mask = sample_mask(val, t)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    es = np.nonzero(mask)[0]
+    ctr = ((np.uint64(t) * np.uint64(nnz) + es.astype(np.uint64))[:, None] * np.uint64(neg_rate)
+           + np.arange(neg_rate, dtype=np.uint64)[None, :])
+    negs = draw_vertex(splitmix64(seed, ctr), n).astype(np.int64)
+    y = Y.tolist()
+
+    def clip(v):
+        return min(CLIP, max(-CLIP, v))
+
+    for q, e in enumerate(es.tolist()):
+        i, j = int(rows[e]), int(col[e])
+        dx, dy = y[i][0] - y[j][0], y[i][1] - y[j][1]
+        d2 = dx * dx + dy * dy
+        if d2 > 0.0:
+            c = -2.0 * a * b * d2 ** (b - 1.0) / (1.0 + a * d2 ** b)
+            gx, gy = clip(c * dx), clip(c * dy)
+            y[i][0] += alpha * gx
+            y[i][1] += alpha * gy
+            y[j][0] -= alpha * gx
+            y[j][1] -= alpha * gy
+        for cv in negs[q].tolist():
+            if cv == i:
+                continue
+            dx, dy = y[i][0] - y[cv][0], y[i][1] - y[cv][1]
+            d2 = dx * dx + dy * dy
+            if d2 > 0.0:
+                c = 2.0 * b / ((EPS_REP + d2) * (1.0 + a * d2 ** b))
+                y[i][0] += alpha * clip(c * dx)
+                y[i][1] += alpha * clip(c * dy)
+    return np.array(y, np.float64)
+
+
+def layout_sequential(Y0, row_ptr, col, val, n_epochs, a, b, alpha0=1.0, neg_rate=5, seed=0):
+    """Every epoch of the sequential form from Y0."""
+    Y = np.asarray(Y0, np.float64)
+    for t in range(n_epochs):
+        Y = layout_epoch_sequential(Y, row_ptr, col, val, t, n_epochs, a, b, alpha0, neg_rate, seed)
+    return Y
+
+
+def fuzzy_cross_entropy(Y, row_ptr, col, val, a, b):
+    """The objective the layout minimises [MHM18] Sec. 3.2: the fuzzy-set
+    cross-entropy between the graph's membership v (0 off the stored
+    pattern) and Phi of the embedding, summed over all unordered pairs
+    {i, j}, i != j (a pair stored in both rows counts once, with the value
+    of row min(i, j)):
+      C = sum v ln(v / Phi) + (1 - v) ln((1 - v) / (1 - Phi)),  0 ln 0 = 0.
+    Dense over the n (n - 1) / 2 pairs: small n only.  Phi is kept inside
+    [1e-12, 1 - 1e-12] so that a pair at distance 0 or far apart stays
+    finite."""
+    Y = np.asarray(Y, np.float64)
+    n = Y.shape[0]
+    V = np.zeros((n, n))
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    V[rows, col.astype(np.int64)] = np.asarray(val, np.float64)
+    iu = np.triu_indices(n, 1)
+    v = V[iu]
+    d2 = ((Y[iu[0]] - Y[iu[1]]) ** 2).sum(1)
+    phi = np.clip(1.0 / (1.0 + a * d2 ** b), 1e-12, 1.0 - 1e-12)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1 = np.where(v > 0.0, v * np.log(np.where(v > 0.0, v, 1.0) / phi), 0.0)
+        t2 = np.where(v < 1.0, (1.0 - v) * np.log(np.where(v < 1.0, 1.0 - v, 1.0) / (1.0 - phi)), 0.0)
+    return float((t1 + t2).sum())
 
 
 def to_scipy(row_ptr, col, val, n):
