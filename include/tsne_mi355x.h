@@ -51,10 +51,21 @@
  *           contents on entry are ignored.
  * Errors.   Arguments are validated before any HIP call; invalid ones
  *           return TSNE_ERR_INVALID_ARG or TSNE_ERR_UNSUPPORTED and enqueue
- *           nothing.  A failed launch returns TSNE_ERR_HIP and its
- *           hipError_t is kept per thread (tsne_last_hip_error).
- *           Asynchronous device faults surface at the caller's next
- *           synchronisation.  No C++ exception crosses the ABI.
+ *           nothing.  Then, before its first launch, a call that does device
+ *           work checks the current HIP device: anything but a gfx950 (or
+ *           no HIP device at all) returns TSNE_ERR_UNSUPPORTED with nothing
+ *           enqueued; the answer is cached per device ordinal.  A failed
+ *           launch returns TSNE_ERR_HIP and its hipError_t is kept per
+ *           thread (tsne_last_hip_error).  Asynchronous device faults
+ *           surface at the caller's next synchronisation.  No C++ exception
+ *           crosses the ABI.
+ * Non-finite inputs.  tsne_knn, tsne_kl_grad, tsne_kl_grad_fft and
+ *           tsne_optimize take a nullable `nonfinite` device int64 scalar:
+ *           the call zeroes it (a fill kernel on `stream`) and its kernels
+ *           add the number of NaN or infinite coordinates they meet, as
+ *           stated per entry point.  The computation itself goes on
+ *           (non-finite values propagate); once the caller has synchronised,
+ *           a nonzero count is the condition TSNE_ERR_NONFINITE names.
  * Threads.  Re-entrant; concurrent calls on different streams with
  *           disjoint buffers are safe.
  * Results.  Deterministic for fixed inputs and device: no floating-point
@@ -70,13 +81,16 @@
 extern "C" {
 #endif
 
-#define TSNE_ABI_VERSION 1
+#define TSNE_ABI_VERSION 2
 
 #define TSNE_OK 0
 #define TSNE_ERR_INVALID_ARG 1
 #define TSNE_ERR_UNSUPPORTED 2
 #define TSNE_ERR_WORKSPACE 3
 #define TSNE_ERR_HIP 4
+/* Not returned by a call (the count is on the device when it returns): the
+ * status a caller reports after reading a nonzero `nonfinite` count. */
+#define TSNE_ERR_NONFINITE 5
 
 /* precision argument of tsne_knn */
 #define TSNE_KNN_FP32 0 /* exact: FP32 direct differences on the VALU */
@@ -118,10 +132,14 @@ int tsne_last_hip_error(void);
  *            bf16 rounding pushes it past rank n_cand.
  *   n_cand   BF16 only: k <= n_cand < n, n_cand <= TSNE_MAX_K (ignored for FP32).
  *   nbr_idx  [n][k] int32 out; nbr_d2 [n][k] float out (FP32 distances).
+ *   nonfinite device int64 scalar out (nullable): the number of NaN or
+ *            infinite entries of X (one extra read of X).  With any, the
+ *            neighbour lists of the rows involved are unspecified.
  *   Invalid: NULL pointers, sizes out of range, unknown precision.
  */
 int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t precision, int32_t n_cand,
-             int32_t* nbr_idx, float* nbr_d2, void* workspace, size_t* workspace_bytes, void* stream);
+             int32_t* nbr_idx, float* nbr_d2, int64_t* nonfinite, void* workspace, size_t* workspace_bytes,
+             void* stream);
 
 /*
  * tsne_calibrate_P -- perplexity calibration [vdMH08 eq. 1 and eq. 3].
@@ -192,10 +210,12 @@ int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64_t n, int3
  *            sum_e p_e ln p_e - sum_e p_e ln w_e + (sum_e p_e) ln Z, always
  *            with the un-exaggerated P (0 ln 0 = 0).
  *   Zrow     [n] double out (nullable): per-row sums Z_i = sum_{j != i} w_ij.
+ *   nonfinite device int64 scalar out (nullable): the number of NaN or
+ *            infinite coordinates of Y.
  */
 int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
-                 float exaggeration, float* grad, double* Z, double* kl, double* Zrow, void* workspace,
-                 size_t* workspace_bytes, void* stream);
+                 float exaggeration, float* grad, double* Z, double* kl, double* Zrow, int64_t* nonfinite,
+                 void* workspace, size_t* workspace_bytes, void* stream);
 
 /*
  * tsne_kl_grad_fft -- the t-SNE gradient of tsne_kl_grad with the repulsive
@@ -220,7 +240,7 @@ int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_
  * so the result is bitwise reproducible.  The grid is set up on the device
  * from Y: the call does not synchronise.
  *
- *   Y, row_ptr, col, val, exaggeration, grad, Z, kl: as tsne_kl_grad.
+ *   Y, row_ptr, col, val, exaggeration, grad, Z, kl, nonfinite: as tsne_kl_grad.
  *   n_interp       p, nodes per box and axis, 2..5 (3).
  *   min_boxes      lower bound of B (>= 1; 50).
  *   max_box_width  upper bound of h while B < max_fft / (2 p) (> 0; 1.0).
@@ -230,7 +250,8 @@ int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_
  */
 int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                      float exaggeration, int32_t n_interp, int32_t min_boxes, float max_box_width, int32_t max_fft,
-                     float* grad, double* Z, double* kl, void* workspace, size_t* workspace_bytes, void* stream);
+                     float* grad, double* Z, double* kl, int64_t* nonfinite, void* workspace,
+                     size_t* workspace_bytes, void* stream);
 
 /*
  * tsne_pca -- principal components of X (the step that produces the PCA
@@ -312,11 +333,15 @@ typedef struct tsne_schedule {
  *             NULL entries skipped): events[2 (t - t_begin)] and [.. + 1] are
  *             recorded on `stream` right before and right after iteration
  *             t's all-pairs repulsion kernel (the dominant cost), for timing.
+ *   nonfinite device int64 scalar out (nullable): the number of NaN or
+ *             infinite coordinates among the positions the iterations
+ *             produce, summed over the iterations (a non-finite input Y
+ *             makes every later position non-finite, so it is counted too).
  */
 int tsne_optimize(float* Y, float* update, float* gains, int64_t n, const int64_t* row_ptr, const int32_t* col,
                   const float* val, int64_t nnz, int32_t t_begin, int32_t t_end, const tsne_schedule* schedule,
-                  int32_t log_every, double* kl_log, void* const* events, void* workspace, size_t* workspace_bytes,
-                  void* stream);
+                  int32_t log_every, double* kl_log, void* const* events, int64_t* nonfinite, void* workspace,
+                  size_t* workspace_bytes, void* stream);
 
 /*
  * Differentiation form.  KL(P||Q) as a function of the embedding Y and of

@@ -16,6 +16,8 @@ TSNE_ERR_INVALID_ARG = 1
 TSNE_ERR_UNSUPPORTED = 2
 TSNE_ERR_WORKSPACE = 3
 TSNE_ERR_HIP = 4
+TSNE_ERR_NONFINITE = 5
+TSNE_ABI_VERSION = 2
 TSNE_KNN_FP32 = 0
 TSNE_KNN_BF16 = 1
 TSNE_F32 = 0
@@ -42,16 +44,16 @@ SIGNATURES = {
     "tsne_abi_version": (C.c_int, []),
     "tsne_status_string": (C.c_char_p, [C.c_int]),
     "tsne_last_hip_error": (C.c_int, []),
-    "tsne_knn": (C.c_int, [_p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _szp, _p]),
+    "tsne_knn": (C.c_int, [_p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _szp, _p]),
     "tsne_calibrate_P": (C.c_int, [_p, _i64, _i32, _f32, _f32, _i32, _p, _p, _p, _p, _p]),
     "tsne_symmetrize": (C.c_int, [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _p, _szp, _p]),
-    "tsne_kl_grad": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _p, _p, _p, _p, _p, _szp, _p]),
-    "tsne_kl_grad_fft": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _i32, _i32, _f32, _i32, _p, _p, _p, _p, _szp,
+    "tsne_kl_grad": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _p, _p, _p, _p, _p, _p, _szp, _p]),
+    "tsne_kl_grad_fft": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _i32, _i32, _f32, _i32, _p, _p, _p, _p, _p, _szp,
                                    _p]),
     "tsne_pca": (C.c_int, [_p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_step": (C.c_int, [_p, _p, _p, _p, _i64, _f32, _f32, _f32, _f32, _f32, _p]),
     "tsne_optimize": (C.c_int, [_p, _p, _p, _i64, _p, _p, _p, _i64, _i32, _i32, C.POINTER(Schedule), _i32, _p, _p,
-                                _p, _szp, _p]),
+                                _p, _p, _szp, _p]),
     "tsne_kl_forward": (C.c_int, [_i32, _p, _i64, _p, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_kl_backward": (C.c_int, [_i32, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_umap_fit_ab": (C.c_int, [C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -90,7 +92,7 @@ def load():
             f = getattr(lib, name)
             f.restype = res
             f.argtypes = args
-        if lib.tsne_abi_version() != 1:
+        if lib.tsne_abi_version() != TSNE_ABI_VERSION:
             raise RuntimeError("libtsne_mi355x ABI version mismatch")
         _lib = lib
     return _lib

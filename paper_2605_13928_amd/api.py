@@ -23,7 +23,8 @@ from ._lib import check
 KLGRAD_FLOPS_PER_ORDERED_PAIR = 8.5
 
 __all__ = ["knn", "calibrate_P", "symmetrize", "kl_grad", "step", "optimize", "kl_forward", "kl_backward",
-           "umap_fit_ab", "umap_weights", "umap_fuzzy_union", "umap_layout", "SparseP", "Workspace"]
+           "umap_fit_ab", "umap_weights", "umap_fuzzy_union", "umap_layout", "SparseP", "Workspace",
+           "nonfinite_counter", "raise_if_nonfinite"]
 
 
 def _ptr(t):
@@ -46,6 +47,19 @@ def _req(t, name, dtype, shape=None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     return t
+
+
+def nonfinite_counter(device) -> torch.Tensor:
+    """A device int64 scalar for the `nonfinite` argument of knn, kl_grad,
+    kl_grad_fft and optimize (the call zeroes it, its kernels count)."""
+    return torch.zeros(1, dtype=torch.int64, device=device)
+
+
+def raise_if_nonfinite(counter: torch.Tensor | None, what: str):
+    """Synchronises on the counter's value and raises TsneError with
+    TSNE_ERR_NONFINITE when it is nonzero."""
+    if counter is not None and int(counter.item()) != 0:
+        raise _lib.TsneError(f"{what} ({int(counter.item())} non-finite coordinates)", _lib.TSNE_ERR_NONFINITE)
 
 
 class Workspace:
@@ -79,8 +93,10 @@ def _run_with_workspace(name, fn, args_before, args_after, device, ws: Workspace
     return buf
 
 
-def knn(X: torch.Tensor, k: int, precision: str = "fp32", n_cand: int | None = None, ws: Workspace | None = None):
-    """Exact kNN of the rows of X [n, d] float32.  Returns (idx int32 [n, k], d2 float32 [n, k])."""
+def knn(X: torch.Tensor, k: int, precision: str = "fp32", n_cand: int | None = None, ws: Workspace | None = None,
+        nonfinite: torch.Tensor | None = None):
+    """Exact kNN of the rows of X [n, d] float32.  Returns (idx int32 [n, k], d2 float32 [n, k]).
+    nonfinite: optional int64 [1] device counter of NaN/inf entries of X."""
     _req(X, "X", torch.float32)
     if X.dim() != 2:
         raise ValueError("X must be [n, d]")
@@ -91,7 +107,10 @@ def knn(X: torch.Tensor, k: int, precision: str = "fp32", n_cand: int | None = N
     idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
     d2 = torch.empty((n, k), dtype=torch.float32, device=X.device)
     L = _lib.load()
-    _run_with_workspace("tsne_knn", L.tsne_knn, (_ptr(X), n, d, k, prec, n_cand, _ptr(idx), _ptr(d2)),
+    if nonfinite is not None:
+        _req(nonfinite, "nonfinite", torch.int64, (1,))
+    _run_with_workspace("tsne_knn", L.tsne_knn,
+                        (_ptr(X), n, d, k, prec, n_cand, _ptr(idx), _ptr(d2), _ptr(nonfinite)),
                         (_stream(X.device),), X.device, ws)
     return idx, d2
 
@@ -150,8 +169,10 @@ def symmetrize(nbr_idx: torch.Tensor, P_cond: torch.Tensor, want_tpos: bool = Tr
 
 
 def kl_grad(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, grad: torch.Tensor | None = None,
-            want_Z: bool = False, want_kl: bool = False, want_Zrow: bool = False, ws: Workspace | None = None):
-    """Exact t-SNE gradient.  Returns (grad [n, 2] f32, Z f64[1] or None, KL f64[1] or None, Zrow f64[n] or None)."""
+            want_Z: bool = False, want_kl: bool = False, want_Zrow: bool = False, ws: Workspace | None = None,
+            nonfinite: torch.Tensor | None = None):
+    """Exact t-SNE gradient.  Returns (grad [n, 2] f32, Z f64[1] or None, KL f64[1] or None, Zrow f64[n] or None).
+    nonfinite: optional int64 [1] device counter of NaN/inf coordinates of Y."""
     _req(Y, "Y", torch.float32)
     n = Y.shape[0]
     if Y.shape != (n, 2) or P.n != n:
@@ -164,16 +185,20 @@ def kl_grad(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, grad: torch.
     Z = torch.empty(1, dtype=torch.float64, device=dev) if want_Z else None
     kl = torch.empty(1, dtype=torch.float64, device=dev) if want_kl else None
     Zrow = torch.empty(n, dtype=torch.float64, device=dev) if want_Zrow else None
+    if nonfinite is not None:
+        _req(nonfinite, "nonfinite", torch.int64, (1,))
     L = _lib.load()
     _run_with_workspace("tsne_kl_grad", L.tsne_kl_grad,
                         (_ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val), float(exaggeration), _ptr(grad),
-                         _ptr(Z), _ptr(kl), _ptr(Zrow)), (_stream(dev),), dev, ws, key=("kl_grad", n, want_Zrow))
+                         _ptr(Z), _ptr(kl), _ptr(Zrow), _ptr(nonfinite)), (_stream(dev),), dev, ws,
+                        key=("kl_grad", n, want_Zrow))
     return grad, Z, kl, Zrow
 
 
 def kl_grad_fft(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, n_interp: int = 3, min_boxes: int = 50,
                 max_box_width: float = 1.0, max_fft: int = 2048, grad: torch.Tensor | None = None,
-                want_Z: bool = False, want_kl: bool = False, ws: Workspace | None = None):
+                want_Z: bool = False, want_kl: bool = False, ws: Workspace | None = None,
+                nonfinite: torch.Tensor | None = None):
     """t-SNE gradient with the repulsion and Z by FFT-accelerated interpolation
     (tsne_kl_grad_fft).  Returns (grad [n, 2] f32, Z f64[1] or None, KL f64[1] or None)."""
     _req(Y, "Y", torch.float32)
@@ -187,10 +212,13 @@ def kl_grad_fft(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, n_interp
         _req(grad, "grad", torch.float32, (n, 2))
     Z = torch.empty(1, dtype=torch.float64, device=dev) if want_Z else None
     kl = torch.empty(1, dtype=torch.float64, device=dev) if want_kl else None
+    if nonfinite is not None:
+        _req(nonfinite, "nonfinite", torch.int64, (1,))
     L = _lib.load()
     _run_with_workspace("tsne_kl_grad_fft", L.tsne_kl_grad_fft,
                         (_ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val), float(exaggeration), int(n_interp),
-                         int(min_boxes), float(max_box_width), int(max_fft), _ptr(grad), _ptr(Z), _ptr(kl)),
+                         int(min_boxes), float(max_box_width), int(max_fft), _ptr(grad), _ptr(Z), _ptr(kl),
+                         _ptr(nonfinite)),
                         (_stream(dev),), dev, ws, key=("kl_grad_fft", n, int(max_fft)))
     return grad, Z, kl
 
@@ -230,13 +258,16 @@ def step(Y, update, gains, grad, lr: float, momentum: float, gain_inc: float = 0
 def optimize(Y, update, gains, P: SparseP, t_begin: int, t_end: int, lr: float = 200.0, exaggeration: float = 12.0,
              exaggeration_iters: int = 100, momentum_early: float = 0.5, momentum_late: float = 0.8,
              gain_inc: float = 0.2, gain_dec: float = 0.8, min_gain: float = 0.01, log_every: int = 0,
-             kl_log: torch.Tensor | None = None, events=None, ws: Workspace | None = None):
+             kl_log: torch.Tensor | None = None, events=None, ws: Workspace | None = None,
+             nonfinite: torch.Tensor | None = None):
     """Iterations t_begin .. t_end-1 (gradient + step each) enqueued by the library.
 
     kl_log: float64 device tensor of t_end - t_begin entries (KL written at
     iterations with (t + 1) % log_every == 0).  events: optional list of
     2 (t_end - t_begin) torch.cuda.Event or None (recorded around each launch
     of the all-pairs repulsion kernel; None entries are skipped).
+    nonfinite: optional int64 [1] device counter of NaN/inf coordinates of
+    the positions the iterations produce (summed over the iterations).
     """
     n = Y.shape[0]
     for t, name in ((Y, "Y"), (update, "update"), (gains, "gains")):
@@ -256,11 +287,14 @@ def optimize(Y, update, gains, P: SparseP, t_begin: int, t_end: int, lr: float =
         ev_arr = C.cast((C.c_void_p * (2 * iters))(*handles), C.c_void_p)
     sc = _lib.Schedule(lr, exaggeration, exaggeration_iters, momentum_early, momentum_late, gain_inc, gain_dec,
                        min_gain)
+    if nonfinite is not None:
+        _req(nonfinite, "nonfinite", torch.int64, (1,))
     dev = Y.device
     L = _lib.load()
     _run_with_workspace("tsne_optimize", L.tsne_optimize,
                         (_ptr(Y), _ptr(update), _ptr(gains), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val),
-                         int(P.nnz), int(t_begin), int(t_end), C.byref(sc), int(log_every), _ptr(kl_log), ev_arr),
+                         int(P.nnz), int(t_begin), int(t_end), C.byref(sc), int(log_every), _ptr(kl_log), ev_arr,
+                         _ptr(nonfinite)),
                         (_stream(dev),), dev, ws, key=("optimize", n, int(P.nnz)))
 
 

@@ -199,6 +199,7 @@ extern "C" int tsne_kl_forward(int32_t dtype, const void* Y, int64_t n, const in
   const KlLayout L = KlLayout::make(n);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
+  TSNE_REQUIRE_GFX950();
   char* ws = static_cast<char*>(workspace);
   hipStream_t s = as_stream(stream);
   if (dtype == TSNE_F32)
@@ -218,6 +219,7 @@ extern "C" int tsne_kl_backward(int32_t dtype, const void* Y, int64_t n, const i
   const KlLayout L = KlLayout::make(n);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
+  TSNE_REQUIRE_GFX950();
   char* ws = static_cast<char*>(workspace);
   hipStream_t s = as_stream(stream);
   if (dtype == TSNE_F32)

@@ -95,6 +95,7 @@ extern "C" int tsne_calibrate_P(const float* nbr_d2, int64_t n, int32_t k, float
   if (!(perplexity > 0.0f) || !(perplexity < float(k)) || !(tol > 0.0f) || max_iter < 1) return TSNE_ERR_INVALID_ARG;
   if (k > TSNE_MAX_K) return TSNE_ERR_UNSUPPORTED;
   if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
+  TSNE_REQUIRE_GFX950();
   hipStream_t s = as_stream(stream);
   if (n_unconverged) {
     int rc = launch_fill<int>(n_unconverged, 1, 0, s);

@@ -14,6 +14,21 @@ void set_last_hip_error(hipError_t e);
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// TSNE_OK when the calling thread's current HIP device is a gfx950, the only
+// architecture the kernels are built for; TSNE_ERR_UNSUPPORTED for any other
+// architecture or when no HIP device is present; TSNE_ERR_HIP when the
+// runtime fails otherwise.  The answer is cached per device ordinal, so only
+// the first call on a device queries its properties.  Enqueues nothing.
+int require_gfx950();
+
+// Returns from the enclosing entry point unless the current device is a
+// gfx950 (after argument validation, before the first launch).
+#define TSNE_REQUIRE_GFX950()                  \
+  do {                                         \
+    const int rc_dev_ = ::tsne::require_gfx950(); \
+    if (rc_dev_ != TSNE_OK) return rc_dev_;    \
+  } while (0)
+
 // Returns TSNE_ERR_HIP from the enclosing entry point if the preceding
 // launch failed.
 #define TSNE_CHECK_LAUNCH()                         \

@@ -635,7 +635,7 @@ int fi_fft2(double2* Cg, int64_t plane, int nch, const FiParams* par, int max_ff
 extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col,
                                 const float* val, float exaggeration, int32_t n_interp, int32_t min_boxes,
                                 float max_box_width, int32_t max_fft, float* grad, double* Z, double* kl,
-                                void* workspace, size_t* workspace_bytes, void* stream) {
+                                int64_t* nonfinite, void* workspace, size_t* workspace_bytes, void* stream) {
   using namespace tsne;
   if (!Y || !row_ptr || !col || !val || !grad || n < 2) return TSNE_ERR_INVALID_ARG;
   if (!(exaggeration > 0.0f) || !(exaggeration < INFINITY)) return TSNE_ERR_INVALID_ARG;
@@ -647,8 +647,11 @@ extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_pt
   const FiPlan L = fi_plan(n, max_fft);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
+  TSNE_REQUIRE_GFX950();
   char* ws = static_cast<char*>(workspace);
   hipStream_t s = as_stream(stream);
+  unsigned long long* nf = reinterpret_cast<unsigned long long*>(nonfinite);
+  if (nf && (rc = launch_fill<unsigned long long>(nf, 1, 0ull, s))) return rc;
   const float2* Y2 = reinterpret_cast<const float2*>(Y);
   float* part = reinterpret_cast<float*>(ws + L.o_part);
   FiParams* par = reinterpret_cast<FiParams*>(ws + L.o_par);
@@ -693,5 +696,5 @@ extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_pt
   if ((rc = fi_fft2(Cg, L.plane, 2, par, max_fft, 1.0, s))) return rc;
   if ((rc = fi_points(n_interp, false, Y2, n, par, off, order, choff, L.nbox, G, Cg, L.plane, R, Zb, s))) return rc;
   return finalize_csr_launch(Y, n, row_ptr, col, val, exaggeration, reinterpret_cast<const float*>(R), Zb, FI_GRID,
-                             grad, Z, kl, klp, s);
+                             grad, Z, kl, klp, nf, s);
 }

@@ -29,7 +29,9 @@ namespace tsne {
 // optimiser step to the row (FusedStep).  Column indices outside [0, n)
 // contribute nothing.  ATTP: the attraction was summed per job by the
 // all-pairs kernel (AttList); it is read from its partial slices, exactly
-// like the repulsion, and the CSR is not touched.
+// like the repulsion, and the CSR is not touched.  nonfinite (nullable):
+// the block adds the number of non-finite coordinates of its rows of Y (with
+// STEP: of its stepped rows, the positions the pass writes).
 constexpr int FIN_ROWS = 16;
 constexpr int FIN_EPT = 8;
 constexpr int FIN_CHUNK = 256 * FIN_EPT;
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     const float* __restrict__ val, float alpha, const float2* __restrict__ Rpart, const float* __restrict__ Zrowpart,
     const float2* __restrict__ Apart, int64_t ns, bool grouped, const double* __restrict__ Zblock, int64_t nZ,
     float2* __restrict__ grad, double* __restrict__ Zrow, double* __restrict__ Z_out, double* __restrict__ klpart,
-    FusedStep st) {
+    FusedStep st, unsigned long long* __restrict__ nonfinite) {
   constexpr int NPR = ATTP ? 5 : 3;  // per-thread sums: R x, R y, Z_row (, A x, A y)
   __shared__ float2 contrib[ATTP ? 1 : FIN_CHUNK];
   __shared__ int64_t rps[FIN_ROWS + 1];
@@ -73,6 +75,11 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     sg = st.G[r0 + tid];
   }
   const double zt = zblock_thread_sum(Zblock, nZ);
+  if (!STEP && nonfinite && tid < 64) {  // wave 0 covers the block's rows
+    const float2 y = (tid < FIN_ROWS && r0 + tid < n) ? Y[r0 + tid] : make_float2(0.0f, 0.0f);
+    const int bad = __popcll(__ballot(!isfinite(y.x))) + __popcll(__ballot(!isfinite(y.y)));
+    if (tid == 0 && bad) atomicAdd(nonfinite, static_cast<unsigned long long>(bad));
+  }
   __syncthreads();
 
   // --- attraction, entry-parallel -----------------------------------------
@@ -213,6 +220,10 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     }
     if (Zrow) Zrow[i] = Zr;
   }
+  if (STEP && nonfinite && tid < 64) {  // the stepped rows (sy is 0 outside them)
+    const int bad = __popcll(__ballot(!isfinite(sy.x))) + __popcll(__ballot(!isfinite(sy.y)));
+    if (tid == 0 && bad) atomicAdd(nonfinite, static_cast<unsigned long long>(bad));
+  }
   if (klpart) {
     const double a = block_sum_d(double(plp), red);
     const double b = block_sum_d(double(plq), red);
@@ -247,14 +258,14 @@ size_t finalize_kl_bytes(int64_t n) { return sizeof(double) * 3 * size_t(ceil_di
 
 int finalize_csr_launch(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                         float alpha, const float* R, const double* Zblock, int64_t nZ, float* grad, double* Z,
-                        double* kl, double* klpart, hipStream_t s) {
+                        double* kl, double* klpart, unsigned long long* nonfinite, hipStream_t s) {
   const int64_t nfin = ceil_div(n, FIN_ROWS);
   double* kp = kl ? klpart : nullptr;
   hipLaunchKernelGGL((finalize_tsne_kernel<false, false>), dim3(unsigned(nfin)), dim3(256), 0, s,
                      reinterpret_cast<const float2*>(Y), n, row_ptr, col, val, alpha,
                      reinterpret_cast<const float2*>(R), static_cast<const float*>(nullptr),
                      static_cast<const float2*>(nullptr), int64_t(1), false, Zblock, nZ,
-                     reinterpret_cast<float2*>(grad), static_cast<double*>(nullptr), Z, kp, FusedStep{});
+                     reinterpret_cast<float2*>(grad), static_cast<double*>(nullptr), Z, kp, FusedStep{}, nonfinite);
   TSNE_CHECK_LAUNCH();
   if (kl) {
     hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, kp, nfin, Zblock, nZ, kl);
@@ -405,7 +416,8 @@ int att_build(const AttPlan& A, const SymGrid& g, char* ws, int64_t n, const int
 
 int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, const int64_t* row_ptr,
                   const int32_t* col, const float* val, float alpha, float* grad, double* Z, double* kl, double* Zrow,
-                  hipStream_t s, const FusedStep* step, hipEvent_t after_repulsion, const AttList* att) {
+                  hipStream_t s, const FusedStep* step, hipEvent_t after_repulsion, const AttList* att,
+                  unsigned long long* nonfinite) {
   const SymGrid& g = L.g;
   const bool fused = att && !Zrow && L.o_A;
   float* Rpart = reinterpret_cast<float*>(ws + L.o_R);
@@ -446,21 +458,21 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
   const bool grp = part_grouped(g.S);
   float2* gr = reinterpret_cast<float2*>(grad);
   const FusedStep st = step ? *step : FusedStep{};
-#define TSNE_FIN(STEP, A, GR, KLP)                                                                          \
+#define TSNE_FIN(STEP, A, GR, KLP, NF)                                                                      \
   hipLaunchKernelGGL((finalize_tsne_kernel<STEP, A>), fgrid, block, 0, s, Y2, n, row_ptr, col, val, alpha, R2, \
-                     Zrowpart, Apart, g.ns, grp, Zblock, g.nwg, GR, Zrow, Z, KLP, st)
+                     Zrowpart, Apart, g.ns, grp, Zblock, g.nwg, GR, Zrow, Z, KLP, st, NF)
   if (fused) {
-    if (step) TSNE_FIN(true, true, nullptr, nullptr);
-    else TSNE_FIN(false, true, gr, nullptr);
+    if (step) TSNE_FIN(true, true, nullptr, nullptr, nonfinite);
+    else TSNE_FIN(false, true, gr, nullptr, nonfinite);
     if (kl) {
       // the KL sums come from the CSR pass, at the same Y; its gradient
       // output goes to scratch, so logging does not change the trajectory
       TSNE_CHECK_LAUNCH();
-      TSNE_FIN(false, false, reinterpret_cast<float2*>(ws + L.o_g), klpart);
+      TSNE_FIN(false, false, reinterpret_cast<float2*>(ws + L.o_g), klpart, nullptr);
     }
   } else {
-    if (step) TSNE_FIN(true, false, nullptr, klpart);
-    else TSNE_FIN(false, false, gr, klpart);
+    if (step) TSNE_FIN(true, false, nullptr, klpart, nonfinite);
+    else TSNE_FIN(false, false, gr, klpart, nonfinite);
   }
 #undef TSNE_FIN
   TSNE_CHECK_LAUNCH();
@@ -474,8 +486,8 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
 }  // namespace tsne
 
 extern "C" int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
-                            float exaggeration, float* grad, double* Z, double* kl, double* Zrow, void* workspace,
-                            size_t* workspace_bytes, void* stream) {
+                            float exaggeration, float* grad, double* Z, double* kl, double* Zrow, int64_t* nonfinite,
+                            void* workspace, size_t* workspace_bytes, void* stream) {
   using namespace tsne;
   if (!Y || !row_ptr || !col || !val || !grad || n < 2) return TSNE_ERR_INVALID_ARG;
   if (!(exaggeration > 0.0f) || !(exaggeration < INFINITY)) return TSNE_ERR_INVALID_ARG;
@@ -483,6 +495,10 @@ extern "C" int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, c
   const KlGradPlan L = klgrad_plan(n);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
-  return klgrad_launch(L, static_cast<char*>(workspace), Y, n, row_ptr, col, val, exaggeration, grad, Z, kl, Zrow,
-                       as_stream(stream));
+  TSNE_REQUIRE_GFX950();
+  hipStream_t s = as_stream(stream);
+  unsigned long long* nf = reinterpret_cast<unsigned long long*>(nonfinite);
+  if (nf && (rc = launch_fill<unsigned long long>(nf, 1, 0ull, s))) return rc;
+  return klgrad_launch(L, static_cast<char*>(workspace), Y, n, row_ptr, col, val, exaggeration, grad, Z, kl, Zrow, s,
+                       nullptr, nullptr, nullptr, nf);
 }

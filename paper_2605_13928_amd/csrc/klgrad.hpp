@@ -55,10 +55,12 @@ int att_build(const AttPlan& A, const SymGrid& g, char* ws, int64_t n, const int
 // With `att` (plan made with_att; Zrow not requested) the attraction is
 // summed inside the all-pairs kernel from the job-grouped list; a requested
 // KL then comes from an extra CSR pass at the same Y.
+// nonfinite (nullable): device counter that receives += the number of
+// non-finite coordinates of Y (with `step`: of the stepped positions).
 int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, const int64_t* row_ptr,
                   const int32_t* col, const float* val, float alpha, float* grad, double* Z, double* kl, double* Zrow,
                   hipStream_t s, const FusedStep* step = nullptr, hipEvent_t after_repulsion = nullptr,
-                  const AttList* att = nullptr);
+                  const AttList* att = nullptr, unsigned long long* nonfinite = nullptr);
 
 // Finalize of a gradient whose repulsion R (one float2 per point) and Z
 // block partials (Z = their sum, in index order) were computed elsewhere:
@@ -67,7 +69,7 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
 size_t finalize_kl_bytes(int64_t n);
 int finalize_csr_launch(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                         float alpha, const float* R, const double* Zblock, int64_t nZ, float* grad, double* Z,
-                        double* kl, double* klpart, hipStream_t s);
+                        double* kl, double* klpart, unsigned long long* nonfinite, hipStream_t s);
 
 // Enqueue one optimiser step (arguments as tsne_step, validated).
 int step_launch(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr, float momentum,

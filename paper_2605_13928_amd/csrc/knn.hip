@@ -552,6 +552,17 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X
   }
 }
 
+// Adds to *out the number of non-finite values among a[0, count): each wave
+// sums its lanes' counts and, if any, adds them with one integer atomic.
+__global__ __launch_bounds__(256) void count_nonfinite_kernel(const float* __restrict__ a, int64_t count,
+                                                              unsigned long long* __restrict__ out) {
+  int c = 0;
+  for (int64_t i = gtid(); i < count; i += int64_t(gridDim.x) * blockDim.x) c += !isfinite(a[i]);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
+  if (__lane_id() == 0 && c) atomicAdd(out, static_cast<unsigned long long>(c));
+}
+
 struct KnnLayout {
   int epl;
   size_t o_buf, o_xq, o_xc, o_cand, bytes;
@@ -577,7 +588,8 @@ struct KnnLayout {
 }  // namespace tsne
 
 extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t precision, int32_t n_cand,
-                        int32_t* nbr_idx, float* nbr_d2, void* workspace, size_t* workspace_bytes, void* stream) {
+                        int32_t* nbr_idx, float* nbr_d2, int64_t* nonfinite, void* workspace, size_t* workspace_bytes,
+                        void* stream) {
   using namespace tsne;
   if (!X || !nbr_idx || !nbr_d2 || n < 2 || d < 1 || k < 1 || k >= n) return TSNE_ERR_INVALID_ARG;
   if (precision != TSNE_KNN_FP32 && precision != TSNE_KNN_BF16) return TSNE_ERR_INVALID_ARG;
@@ -588,9 +600,18 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   const KnnLayout L = KnnLayout::make(n, k, precision, n_cand);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
+  TSNE_REQUIRE_GFX950();
   char* ws = static_cast<char*>(workspace);
   uint64_t* bufs = reinterpret_cast<uint64_t*>(ws + L.o_buf);
   hipStream_t s = as_stream(stream);
+  if (nonfinite) {
+    unsigned long long* nf = reinterpret_cast<unsigned long long*>(nonfinite);
+    if ((rc = launch_fill<unsigned long long>(nf, 1, 0ull, s))) return rc;
+    const int64_t cnt = n * int64_t(d);
+    const int64_t blocks = ceil_div(cnt, 256) < 2048 ? ceil_div(cnt, 256) : 2048;
+    hipLaunchKernelGGL(count_nonfinite_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, X, cnt, nf);
+    TSNE_CHECK_LAUNCH();
+  }
   if (precision == TSNE_KNN_FP32) {
     if (fknn_small_blocks(n))
       hipLaunchKernelGGL((knn_fp32_kernel<8, 8>), dim3(unsigned(ceil_div(n, 32))), dim3(256), 0, s, X, n, d, k, bufs,

@@ -16,7 +16,7 @@
 extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, const int64_t* row_ptr,
                              const int32_t* col, const float* val, int64_t nnz, int32_t t_begin, int32_t t_end,
                              const tsne_schedule* schedule, int32_t log_every, double* kl_log, void* const* events,
-                             void* workspace, size_t* workspace_bytes, void* stream) {
+                             int64_t* nonfinite, void* workspace, size_t* workspace_bytes, void* stream) {
   using namespace tsne;
   if (!Y || !update || !gains || !row_ptr || !col || !val || !schedule || n < 2 || nnz < 0) return TSNE_ERR_INVALID_ARG;
   if (t_begin < 0 || t_end < t_begin || log_every < 0) return TSNE_ERR_INVALID_ARG;
@@ -31,10 +31,13 @@ extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, c
   const size_t o_att = c.take(A.bytes);
   int rc = workspace_protocol(workspace, workspace_bytes, c.off);
   if (rc >= 0) return rc;
+  TSNE_REQUIRE_GFX950();
   char* ws = static_cast<char*>(workspace);
   float* ycur = Y;
   float* ynext = reinterpret_cast<float*>(ws + o_y);
   hipStream_t s = as_stream(stream);
+  unsigned long long* nf = reinterpret_cast<unsigned long long*>(nonfinite);
+  if (nf && (rc = launch_fill<unsigned long long>(nf, 1, 0ull, s))) return rc;
   AttList att;
   if (t_end > t_begin && (rc = att_build(A, L.g, ws + o_att, n, row_ptr, col, val, &att, s))) return rc;
   for (int32_t t = t_begin; t < t_end; ++t) {
@@ -51,7 +54,7 @@ extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, c
                        reinterpret_cast<float2*>(gains), sc.lr, mom, sc.gain_inc, sc.gain_dec, sc.min_gain};
     rc = klgrad_launch(L, ws + o_kg, ycur, n, row_ptr, col, val, alpha, nullptr, nullptr,
                        log ? kl_log + slot : nullptr, nullptr, s, &st,
-                       events ? static_cast<hipEvent_t>(events[2 * slot + 1]) : nullptr, &att);
+                       events ? static_cast<hipEvent_t>(events[2 * slot + 1]) : nullptr, &att, nf);
     if (rc) return rc;
     float* tmp = ycur;
     ycur = ynext;

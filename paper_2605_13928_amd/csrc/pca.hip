@@ -720,6 +720,7 @@ extern "C" int tsne_pca(const float* X, int64_t n, int32_t g, int32_t k, int32_t
   const PcaPlan L = pca_plan(n, g);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
+  TSNE_REQUIRE_GFX950();
   const PcaCtx x{L, static_cast<char*>(workspace), as_stream(stream)};
   float* Ya = x.at<float>(L.o_Ya);
   float* Yb = x.at<float>(L.o_Yb);

@@ -35,6 +35,7 @@ extern "C" int tsne_step(float* Y, float* update, float* gains, const float* gra
                          float momentum, float gain_inc, float gain_dec, float min_gain, void* stream) {
   if (!Y || !update || !gains || !grad || n < 1) return TSNE_ERR_INVALID_ARG;
   if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
+  TSNE_REQUIRE_GFX950();
   return tsne::step_launch(Y, update, gains, grad, n, lr, momentum, gain_inc, gain_dec, min_gain,
                            tsne::as_stream(stream));
 }

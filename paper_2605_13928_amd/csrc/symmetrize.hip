@@ -377,6 +377,7 @@ int symmetrize_impl(const int32_t* nbr_idx, const float* P_cond, int64_t n, int3
   const SymLayout L = SymLayout::make(n, k);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
+  TSNE_REQUIRE_GFX950();
   char* ws = static_cast<char*>(workspace);
   int* indeg = reinterpret_cast<int*>(ws + L.o_indeg);
   int* cursor = reinterpret_cast<int*>(ws + L.o_cursor);

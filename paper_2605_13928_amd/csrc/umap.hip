@@ -349,6 +349,7 @@ extern "C" int tsne_umap_weights(const float* nbr_d2, int64_t n, int32_t k, floa
   using namespace tsne;
   if (!nbr_d2 || !rho || !sigma || !w || n < 1 || k < 1) return TSNE_ERR_INVALID_ARG;
   if (k > TSNE_MAX_K) return TSNE_ERR_UNSUPPORTED;
+  TSNE_REQUIRE_GFX950();
   hipLaunchKernelGGL(umap_weights_kernel, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, as_stream(stream), nbr_d2,
                      n, k, rho, sigma, w);
   TSNE_CHECK_LAUNCH();
@@ -368,6 +369,7 @@ extern "C" int tsne_umap_layout(float* Y, int64_t n, const int64_t* row_ptr, con
   const UmapLayout L = UmapLayout::make(n);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
+  TSNE_REQUIRE_GFX950();
   char* ws = static_cast<char*>(workspace);
   float* part = reinterpret_cast<float*>(ws + L.o_part);
   float* wmax = reinterpret_cast<float*>(ws + L.o_wmax);
