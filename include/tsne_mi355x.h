@@ -81,7 +81,7 @@
 extern "C" {
 #endif
 
-#define TSNE_ABI_VERSION 2
+#define TSNE_ABI_VERSION 3
 
 #define TSNE_OK 0
 #define TSNE_ERR_INVALID_ARG 1
@@ -91,6 +91,8 @@ extern "C" {
 /* Not returned by a call (the count is on the device when it returns): the
  * status a caller reports after reading a nonzero `nonfinite` count. */
 #define TSNE_ERR_NONFINITE 5
+/* tsne_kl_grad_noalloc: the problem needs more than its static scratch. */
+#define TSNE_ERR_SCRATCH 6
 
 /* precision argument of tsne_knn */
 #define TSNE_KNN_FP32 0 /* exact: FP32 direct differences on the VALU */
@@ -216,6 +218,33 @@ int tsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64_t n, int3
 int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                  float exaggeration, float* grad, double* Z, double* kl, double* Zrow, int64_t* nonfinite,
                  void* workspace, size_t* workspace_bytes, void* stream);
+
+/*
+ * tsne_kl_grad_noalloc -- tsne_kl_grad for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels, the same results bit
+ * for bit, but the scratch is a static device array of
+ * TSNE_NOALLOC_SCRATCH_BYTES held by the library on every device it runs on
+ * until the process ends, instead of a caller workspace.  The call allocates
+ * and frees nothing.  The caller still passes the inputs and outputs.
+ *   Arguments as tsne_kl_grad, without workspace.
+ *   Limit: the scratch must hold the repulsion partials (8 B per point and
+ *   superblock of the all-pairs pass), plus 4 B per point and superblock
+ *   when Zrow is requested; it does whenever tsne_kl_grad's own workspace
+ *   query answers at most TSNE_NOALLOC_SCRATCH_BYTES, and in all for
+ *   n <= 92,160 (Zrow NULL) or n <= 53,248 (Zrow given).  Larger problems
+ *   return TSNE_ERR_SCRATCH before any HIP call.
+ *   The first call on a device looks up the scratch's device address there
+ *   (hipGetSymbolAddress, with that device current) and keeps it.
+ *   Every call on one device shares that device's scratch: calls that
+ *   overlap in time on one device (different streams or threads) race and
+ *   give undefined results.  Nothing in the scratch needs to start at zero.
+ */
+#define TSNE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+int tsne_kl_grad_noalloc(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
+                         float exaggeration, float* grad, double* Z, double* kl, double* Zrow, int64_t* nonfinite,
+                         void* stream);
 
 /*
  * tsne_kl_grad_fft -- the t-SNE gradient of tsne_kl_grad with the repulsive

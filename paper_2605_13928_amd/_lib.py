@@ -17,7 +17,8 @@ TSNE_ERR_UNSUPPORTED = 2
 TSNE_ERR_WORKSPACE = 3
 TSNE_ERR_HIP = 4
 TSNE_ERR_NONFINITE = 5
-TSNE_ABI_VERSION = 2
+TSNE_ERR_SCRATCH = 6
+TSNE_ABI_VERSION = 3
 TSNE_KNN_FP32 = 0
 TSNE_KNN_BF16 = 1
 TSNE_F32 = 0
@@ -48,6 +49,7 @@ SIGNATURES = {
     "tsne_calibrate_P": (C.c_int, [_p, _i64, _i32, _f32, _f32, _i32, _p, _p, _p, _p, _p]),
     "tsne_symmetrize": (C.c_int, [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _p, _szp, _p]),
     "tsne_kl_grad": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _p, _p, _p, _p, _p, _p, _szp, _p]),
+    "tsne_kl_grad_noalloc": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _p, _p, _p, _p, _p, _p]),
     "tsne_kl_grad_fft": (C.c_int, [_p, _i64, _p, _p, _p, _f32, _i32, _i32, _f32, _i32, _p, _p, _p, _p, _p, _szp,
                                    _p]),
     "tsne_pca": (C.c_int, [_p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p, _szp, _p]),

@@ -22,7 +22,7 @@ from ._lib import check
 # (force on i and on j) = 17 flops, i.e. 8.5 per ordered pair.
 KLGRAD_FLOPS_PER_ORDERED_PAIR = 8.5
 
-__all__ = ["knn", "calibrate_P", "symmetrize", "kl_grad", "step", "optimize", "kl_forward", "kl_backward",
+__all__ = ["knn", "calibrate_P", "symmetrize", "kl_grad", "kl_grad_noalloc", "step", "optimize", "kl_forward", "kl_backward",
            "umap_fit_ab", "umap_weights", "umap_fuzzy_union", "umap_layout", "SparseP", "Workspace",
            "nonfinite_counter", "raise_if_nonfinite"]
 
@@ -192,6 +192,32 @@ def kl_grad(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, grad: torch.
                         (_ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val), float(exaggeration), _ptr(grad),
                          _ptr(Z), _ptr(kl), _ptr(Zrow), _ptr(nonfinite)), (_stream(dev),), dev, ws,
                         key=("kl_grad", n, want_Zrow))
+    return grad, Z, kl, Zrow
+
+
+def kl_grad_noalloc(Y: torch.Tensor, P: SparseP, exaggeration: float = 1.0, grad: torch.Tensor | None = None,
+                    Z: torch.Tensor | None = None, kl: torch.Tensor | None = None, Zrow: torch.Tensor | None = None,
+                    nonfinite: torch.Tensor | None = None):
+    """tsne_kl_grad_noalloc: kl_grad on the library's static device scratch (no
+    workspace).  Outputs are the caller's tensors when given (grad [n, 2] f32,
+    Z and kl f64 [1], Zrow f64 [n]); a missing grad is allocated here, the
+    others are then not computed.  Returns (grad, Z, kl, Zrow)."""
+    _req(Y, "Y", torch.float32)
+    n = Y.shape[0]
+    if Y.shape != (n, 2) or P.n != n:
+        raise ValueError("Y must be [n, 2] matching P")
+    if grad is None:
+        grad = torch.empty_like(Y)
+    _req(grad, "grad", torch.float32, (n, 2))
+    for t, name, shape in ((Z, "Z", (1,)), (kl, "kl", (1,)), (Zrow, "Zrow", (n,))):
+        if t is not None:
+            _req(t, name, torch.float64, shape)
+    if nonfinite is not None:
+        _req(nonfinite, "nonfinite", torch.int64, (1,))
+    L = _lib.load()
+    check("tsne_kl_grad_noalloc",
+          L.tsne_kl_grad_noalloc(_ptr(Y), n, _ptr(P.row_ptr), _ptr(P.col), _ptr(P.val), float(exaggeration),
+                                 _ptr(grad), _ptr(Z), _ptr(kl), _ptr(Zrow), _ptr(nonfinite), _stream(Y.device)))
     return grad, Z, kl, Zrow
 
 

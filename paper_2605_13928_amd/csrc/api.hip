@@ -54,6 +54,7 @@ extern "C" const char* tsne_status_string(int status) {
     case TSNE_ERR_WORKSPACE: return "workspace too small";
     case TSNE_ERR_HIP: return "HIP launch error";
     case TSNE_ERR_NONFINITE: return "non-finite (NaN or infinite) input coordinates";
+    case TSNE_ERR_SCRATCH: return "problem too large for the static scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

@@ -10,6 +10,8 @@
 #include "rep_sym.hpp"
 #include "scan.hpp"
 
+#include <mutex>
+
 namespace tsne {
 
 // Finalize, 16 rows per block.
@@ -274,14 +276,15 @@ int finalize_csr_launch(const float* Y, int64_t n, const int64_t* row_ptr, const
   return TSNE_OK;
 }
 
-KlGradPlan klgrad_plan(int64_t n, bool with_att) {
+KlGradPlan klgrad_plan(int64_t n, bool with_att, bool with_zrow) {
   KlGradPlan L;
   L.g = SymGrid::make(n);
   L.nfin = ceil_div(n, FIN_ROWS);
+  L.zrow = with_zrow;
   Carve c;
   const size_t n16 = size_t(ceil_div(n, 16)) * 16;
   L.o_R = c.take(sizeof(float2) * size_t(L.g.ns) * n16);
-  L.o_Zr = c.take(sizeof(float) * size_t(L.g.ns) * n16);
+  L.o_Zr = with_zrow ? c.take(sizeof(float) * size_t(L.g.ns) * n16) : 0;
   L.o_Zb = c.take(sizeof(double) * size_t(L.g.nwg));
   L.o_kl = c.take(sizeof(double) * 3 * size_t(L.nfin));
   L.o_A = with_att ? c.take(sizeof(float2) * size_t(L.g.ns) * n16) : 0;
@@ -419,6 +422,7 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
                   hipStream_t s, const FusedStep* step, hipEvent_t after_repulsion, const AttList* att,
                   unsigned long long* nonfinite) {
   const SymGrid& g = L.g;
+  if (Zrow && !L.zrow) return TSNE_ERR_INVALID_ARG;  // plan without room for the per-row Z partials
   const bool fused = att && !Zrow && L.o_A;
   float* Rpart = reinterpret_cast<float*>(ws + L.o_R);
   float* Zrowpart = Zrow ? reinterpret_cast<float*>(ws + L.o_Zr) : nullptr;
@@ -485,20 +489,89 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
 
 }  // namespace tsne
 
+namespace tsne {
+
+// Argument checks shared by tsne_kl_grad and tsne_kl_grad_noalloc.
+static int kl_grad_args(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
+                        float exaggeration, float* grad) {
+  if (!Y || !row_ptr || !col || !val || !grad || n < 2) return TSNE_ERR_INVALID_ARG;
+  if (!(exaggeration > 0.0f) || !(exaggeration < INFINITY)) return TSNE_ERR_INVALID_ARG;
+  if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
+  return TSNE_OK;
+}
+
+// The launches of one gradient evaluation on workspace `ws` (plan L).
+static int kl_grad_enqueue(const KlGradPlan& L, char* ws, const float* Y, int64_t n, const int64_t* row_ptr,
+                           const int32_t* col, const float* val, float exaggeration, float* grad, double* Z,
+                           double* kl, double* Zrow, int64_t* nonfinite, hipStream_t s) {
+  unsigned long long* nf = reinterpret_cast<unsigned long long*>(nonfinite);
+  int rc;
+  if (nf && (rc = launch_fill<unsigned long long>(nf, 1, 0ull, s))) return rc;
+  return klgrad_launch(L, ws, Y, n, row_ptr, col, val, exaggeration, grad, Z, kl, Zrow, s, nullptr, nullptr, nullptr,
+                       nf);
+}
+
+// Scratch of tsne_kl_grad_noalloc, for callers that cannot allocate.  Each
+// device holds its own copy for the life of the process.  In host code the
+// name `scratch` is only a host-side handle, not a device address: the
+// address the kernels get is the one hipGetSymbolAddress returns on each
+// device, looked up once per device (with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[TSNE_NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_addr[SCRATCH_MAX_DEVICES];
+
+// Device address of `scratch` on the current device.
+static int scratch_address(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_last_hip_error(e);
+    return TSNE_ERR_HIP;
+  }
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return TSNE_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_last_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return TSNE_ERR_HIP;
+    }
+    g_scratch_addr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return TSNE_OK;
+}
+
+}  // namespace tsne
+
 extern "C" int tsne_kl_grad(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                             float exaggeration, float* grad, double* Z, double* kl, double* Zrow, int64_t* nonfinite,
                             void* workspace, size_t* workspace_bytes, void* stream) {
   using namespace tsne;
-  if (!Y || !row_ptr || !col || !val || !grad || n < 2) return TSNE_ERR_INVALID_ARG;
-  if (!(exaggeration > 0.0f) || !(exaggeration < INFINITY)) return TSNE_ERR_INVALID_ARG;
-  if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
+  int rc = kl_grad_args(Y, n, row_ptr, col, val, exaggeration, grad);
+  if (rc != TSNE_OK) return rc;
   const KlGradPlan L = klgrad_plan(n);
-  int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
+  rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
   TSNE_REQUIRE_GFX950();
-  hipStream_t s = as_stream(stream);
-  unsigned long long* nf = reinterpret_cast<unsigned long long*>(nonfinite);
-  if (nf && (rc = launch_fill<unsigned long long>(nf, 1, 0ull, s))) return rc;
-  return klgrad_launch(L, static_cast<char*>(workspace), Y, n, row_ptr, col, val, exaggeration, grad, Z, kl, Zrow, s,
-                       nullptr, nullptr, nullptr, nf);
+  return kl_grad_enqueue(L, static_cast<char*>(workspace), Y, n, row_ptr, col, val, exaggeration, grad, Z, kl, Zrow,
+                         nonfinite, as_stream(stream));
+}
+
+extern "C" int tsne_kl_grad_noalloc(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                                    const float* val, float exaggeration, float* grad, double* Z, double* kl,
+                                    double* Zrow, int64_t* nonfinite, void* stream) {
+  using namespace tsne;
+  int rc = kl_grad_args(Y, n, row_ptr, col, val, exaggeration, grad);
+  if (rc != TSNE_OK) return rc;
+  const KlGradPlan L = klgrad_plan(n, false, Zrow != nullptr);
+  if (L.bytes > TSNE_NOALLOC_SCRATCH_BYTES) return TSNE_ERR_SCRATCH;
+  TSNE_REQUIRE_GFX950();
+  char* ws = nullptr;
+  if ((rc = scratch_address(&ws)) != TSNE_OK) return rc;
+  return kl_grad_enqueue(L, ws, Y, n, row_ptr, col, val, exaggeration, grad, Z, kl, Zrow, nonfinite,
+                         as_stream(stream));
 }

@@ -32,12 +32,14 @@ struct FusedStep {
 struct KlGradPlan {
   SymGrid g;
   int64_t nfin;
+  bool zrow;  // o_Zr is valid (the per-row Z partials have room)
   size_t o_R, o_Zr, o_Zb, o_kl, o_A, o_g, bytes;  // o_A, o_g: attraction partials, scratch gradient (with_att)
 };
 
 // Workspace layout of one gradient evaluation for n points; with_att adds
-// the attraction partials of the fused path (AttList).
-KlGradPlan klgrad_plan(int64_t n, bool with_att = false);
+// the attraction partials of the fused path (AttList), with_zrow the
+// per-row Z partials (needed only when Zrow is requested).
+KlGradPlan klgrad_plan(int64_t n, bool with_att = false, bool with_zrow = true);
 
 // Workspace layout and build of the job-grouped attraction list of a CSR P
 // with nnz stored entries (unordered pairs i < j; see AttList).
@@ -52,7 +54,8 @@ int att_build(const AttPlan& A, const SymGrid& g, char* ws, int64_t n, const int
 // With `step`, the finalize pass applies the optimiser step to every row
 // instead of writing the gradient (grad may then be null).  after_repulsion
 // (nullable) is recorded on s between the all-pairs pass and the finalize.
-// With `att` (plan made with_att; Zrow not requested) the attraction is
+// Zrow needs a plan made with_zrow.  With `att` (plan made with_att; Zrow
+// not requested) the attraction is
 // summed inside the all-pairs kernel from the job-grouped list; a requested
 // KL then comes from an extra CSR pass at the same Y.
 // nonfinite (nullable): device counter that receives += the number of

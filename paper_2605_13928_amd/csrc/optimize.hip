@@ -23,7 +23,7 @@ extern "C" int tsne_optimize(float* Y, float* update, float* gains, int64_t n, c
   const tsne_schedule sc = *schedule;
   if (!(sc.exaggeration > 0.0f) || !(sc.exaggeration < INFINITY) || !(sc.lr > 0.0f)) return TSNE_ERR_INVALID_ARG;
   if (n > (int64_t(1) << 31)) return TSNE_ERR_UNSUPPORTED;
-  const KlGradPlan L = klgrad_plan(n, true);
+  const KlGradPlan L = klgrad_plan(n, true, false);  // Zrow is never requested here
   const AttPlan A = att_plan(L.g, nnz);
   Carve c;
   const size_t o_kg = c.take(L.bytes);

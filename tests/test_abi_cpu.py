@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
-    assert L.tsne_abi_version() == 2 == _lib.TSNE_ABI_VERSION
+    assert L.tsne_abi_version() == 3 == _lib.TSNE_ABI_VERSION
     assert L.tsne_status_string(3).decode() == "workspace too small"
 
 
@@ -58,6 +58,18 @@ def test_workspace_queries_need_no_device(L):
         assert rc == 0 and need > 0
         rc, need = ws_query(L.tsne_kl_backward, dt, fake, 64, fake, fake, fake, fake, fake, fake, NULL)
         assert rc == 0 and need > 0
+
+
+def test_noalloc_rejects_oversized_problems_before_any_hip_call(L):
+    fake = C.c_void_p(0x1000)
+    nz = None
+    g = L.tsne_kl_grad_noalloc
+    assert g(fake, 92_161, fake, fake, fake, C.c_float(1.0), fake, nz, nz, nz, nz, nz) == _lib.TSNE_ERR_SCRATCH
+    assert g(fake, 53_249, fake, fake, fake, C.c_float(1.0), fake, nz, nz, fake, nz, nz) == _lib.TSNE_ERR_SCRATCH
+    assert g(fake, 1, fake, fake, fake, C.c_float(1.0), fake, nz, nz, nz, nz, nz) == _lib.TSNE_ERR_INVALID_ARG
+    assert g(fake, 10, fake, fake, fake, C.c_float(0.0), fake, nz, nz, nz, nz, nz) == _lib.TSNE_ERR_INVALID_ARG
+    assert g(fake, 10, fake, fake, fake, C.c_float(1.0), nz, nz, nz, nz, nz, nz) == _lib.TSNE_ERR_INVALID_ARG
+    assert L.tsne_status_string(_lib.TSNE_ERR_SCRATCH).decode().startswith("problem too large")
 
 
 def test_too_small_workspace_is_rejected_before_launch(L):
