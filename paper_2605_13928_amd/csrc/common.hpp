@@ -100,28 +100,71 @@ __device__ __forceinline__ float row16_min(float v) {
   return v;
 }
 
-__device__ __forceinline__ double shfl_xor_d(double v, int m) {
-  int lo = __shfl_xor(int(__double2loint(v)), m);
-  int hi = __shfl_xor(int(__double2hiint(v)), m);
-  return __hiloint2double(hi, lo);
+// Value held by lane (lane ^ M), M a power of two below 64, with no trip
+// through the LDS unit: DPP quad permutations (M = 1, 2), two DPP row shifts
+// and a select (M = 4), a DPP row rotation (M = 8), and gfx950's
+// v_permlane16_swap / v_permlane32_swap (M = 16, 32: with both operands v,
+// the first result holds the lower row / half in both places, the second
+// the upper one).
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  static_assert(M == 1 || M == 2 || M == 4 || M == 8 || M == 16 || M == 32, "power of two below 64");
+  const int x = int(v);
+  if constexpr (M == 1) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false));  // quad_perm [1, 0, 3, 2]
+  } else if constexpr (M == 2) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false));  // quad_perm [2, 3, 0, 1]
+  } else if constexpr (M == 4) {
+    const int up = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xf, 0xf, false);  // row_shl:4, lane i <- i + 4
+    const int dn = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4, lane i <- i - 4
+    return uint32_t((lane_id() & 4) ? dn : up);
+  } else if constexpr (M == 8) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xf, 0xf, false));  // row_ror:8
+  } else if constexpr (M == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane_id() & 16) ? r[0] : r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane_id() & 32) ? r[0] : r[1];
+  }
 }
+// The same for a mask known only after unrolling.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int m) {
+  switch (m) {
+    case 1: return xor_lane<1>(v);
+    case 2: return xor_lane<2>(v);
+    case 4: return xor_lane<4>(v);
+    case 8: return xor_lane<8>(v);
+    case 16: return xor_lane<16>(v);
+    default: return xor_lane<32>(v);
+  }
+}
+__device__ __forceinline__ float xor_lane_f(float v, int m) { return __uint_as_float(xor_lane(__float_as_uint(v), m)); }
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  uint32_t lo = __shfl_xor(uint32_t(v), m);
-  uint32_t hi = __shfl_xor(uint32_t(v >> 32), m);
+  const uint32_t lo = xor_lane(uint32_t(v), m);
+  const uint32_t hi = xor_lane(uint32_t(v >> 32), m);
   return (uint64_t(hi) << 32) | lo;
+}
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  return __builtin_bit_cast(double, shfl_xor_u64(__builtin_bit_cast(uint64_t, v), m));
 }
 
 // Whole-wave reductions; all 64 lanes return the same bits.
 __device__ __forceinline__ float wave_sum(float v) {
   v = row16_sum(v);
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
+  v += xor_lane_f(v, 16);
+  v += xor_lane_f(v, 32);
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v += int(xor_lane(uint32_t(v), m));
   return v;
 }
 __device__ __forceinline__ float wave_min(float v) {
   v = row16_min(v);
-  v = fminf(v, __shfl_xor(v, 16));
-  v = fminf(v, __shfl_xor(v, 32));
+  v = fminf(v, xor_lane_f(v, 16));
+  v = fminf(v, xor_lane_f(v, 32));
   return v;
 }
 __device__ __forceinline__ double wave_sum_d(double v) {

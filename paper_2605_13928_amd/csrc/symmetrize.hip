@@ -75,7 +75,8 @@ __device__ void wave_bitonic_segment(const int32_t* __restrict__ key, const floa
   for (int t = 0; t < EPL; ++t) {
     const int e = t * 64 + lane;
     const uint32_t hi = uint32_t(v[t] >> 32);
-    uint32_t before = __shfl_up(hi, 1);  // source of element e - 1 (same register)
+    // source of element e - 1 (same register): DPP wave_shr:1, lane l <- l - 1
+    uint32_t before = uint32_t(__builtin_amdgcn_update_dpp(0, int(hi), 0x138, 0xf, 0xf, false));
     if (lane == 0) before = prev_last;   // ... or the last lane of the previous register
     if (e > 0 && e < len && before == hi) rep = true;
     prev_last = __builtin_amdgcn_readlane(hi, 63);
