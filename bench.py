@@ -112,7 +112,7 @@ def traffic_from_profile(digest, workload):
     if vals.get("source_digest") != digest:
         return None
     try:
-        return float(vals["hbm_bytes_per_call"])
+        return float(vals["hbm_bytes_per_call"].split()[0])
     except (KeyError, ValueError):
         return None
 

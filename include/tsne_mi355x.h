@@ -354,6 +354,11 @@ typedef struct tsne_schedule {
  *                     and every row summing to at most 1 (true for the
  *                     output of tsne_symmetrize).
  *   nnz       stored entries of P (row_ptr[n]); it sizes the workspace.
+ *             The call cannot read row_ptr[n] without synchronising, so it
+ *             trusts nnz: a larger value only enlarges the workspace; a
+ *             smaller one leaves the job-grouped copy of P too short, and
+ *             the entries past its end are dropped from the attraction
+ *             (no fault, but not the gradient stated above).
  *   schedule  host pointer, read before the call returns.
  *   kl_log    device double array of (t_end - t_begin) entries (nullable):
  *             with log_every > 0, entry t - t_begin receives KL(P||Q) for the

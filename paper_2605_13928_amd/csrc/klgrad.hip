@@ -95,8 +95,10 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     for (int m = 0; m < FIN_EPT; ++m) {
       const int64_t e = c0 + tid + 256 * m;
       const bool ok = e < E1;
-      jj[m] = ok ? col[e] : 0;
-      pp[m] = ok ? val[e] : 0.0f;
+      // read once: non-temporal, so the stream of entries does not evict the
+      // gathered rows of Y from L2
+      jj[m] = ok ? __builtin_nontemporal_load(col + e) : 0;
+      pp[m] = ok ? __builtin_nontemporal_load(val + e) : 0.0f;
     }
 #pragma unroll
     for (int m = 0; m < FIN_EPT; ++m) {

@@ -15,11 +15,16 @@
 // tau by a radix select, keeps the keys with d <= tau and makes tau the
 // new threshold.  The true k best always satisfy d <= tau, so nothing is
 // lost; ties at tau are kept and resolved by index in the final sort (a
-// wave-wide bitonic sort of the (d, j) keys).
+// wave-wide bitonic sort of the (d, j) keys).  Since the kept keys are the
+// best ones whatever order the candidates arrive in, the BF16 path sweeps
+// them in a locality order (points sorted by a Morton key of their leading
+// coordinates, each query block starting next to its own queries), so that
+// tau is tight after a few tiles and few candidates are appended.
 #include <cfloat>
 #include <type_traits>
 
 #include "common.hpp"
+#include "scan.hpp"
 
 namespace tsne {
 
@@ -31,14 +36,17 @@ namespace tsne {
 // write-back or invalidation beyond the CU.
 __device__ __forceinline__ void wg_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
+// Inclusive prefix sum over the 64 lanes of a wave, in DPP: shifts by 1, 2,
+// 4 and 8 within each row of 16 (lanes shifted in from outside the row add
+// 0), then row 0's total into row 1 and row 2's into row 3 (row_bcast:15),
+// then lane 31's running total into rows 2 and 3 (row_bcast:31).
 __device__ __forceinline__ int wave_incl_scan(int x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1 and 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2 and 3
   return x;
 }
 
@@ -306,15 +314,118 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(
 constexpr uint16_t BF16_ONE = 0x3F80;
 constexpr uint16_t BF16_INF = 0x7F80;
 
-// One wave per row.  Query row:     [x~ (d), nh, nm, nl, 1, 1, 1, 0 ...]
-//                   candidate row:  [-2 x~ (d), 1, 1, 1, nh, nm, nl, 0 ...]
+// Locality order of the BF16 path.  Points are counting-sorted by a 16-bit
+// Morton key of their first three coordinates (6, 5 and 5 bits over each
+// coordinate's range; fewer coordinates when d < 3): position p of the
+// sorted order holds point perm[p].  Within a key the order is that of the
+// scatter's atomics; nothing downstream depends on it (the selection keeps
+// the best keys (d, original index) whatever order they arrive in).
+constexpr int LOC_BINS = 1 << 16;
+constexpr int LOC_DIMS = 3;
+constexpr int LOC_BITS[LOC_DIMS] = {6, 5, 5};
+
+// float <-> unsigned int with the same order, for integer atomic min / max
+__device__ __forceinline__ uint32_t f_ord(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord_f(uint32_t u) { return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u); }
+
+// rng[c] = min and rng[LOC_DIMS + c] = max (order-encoded) of the finite
+// values of coordinate c < min(d, 3); rng starts at {~0 x 3, 0 x 3}.
+__global__ __launch_bounds__(256) void loc_range_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                        uint32_t* __restrict__ rng) {
+  const int nd = d < LOC_DIMS ? d : LOC_DIMS;
+  float mn[LOC_DIMS], mx[LOC_DIMS];
+#pragma unroll
+  for (int c = 0; c < LOC_DIMS; ++c) {
+    mn[c] = INFINITY;
+    mx[c] = -INFINITY;
+  }
+  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < LOC_DIMS; ++c) {
+      if (c < nd) {
+        const float v = X[i * d + c];
+        if (isfinite(v)) {
+          mn[c] = fminf(mn[c], v);
+          mx[c] = fmaxf(mx[c], v);
+        }
+      }
+    }
+  }
+  // the block's extremes (waves, then wave 0 over the four), one atomic per
+  // block and bound: the grid is small, so few atomics meet at one address
+  __shared__ float part[4][2 * LOC_DIMS];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < LOC_DIMS; ++c) {
+    const float a = wave_min(mn[c]), b = -wave_min(-mx[c]);
+    if (lane_id() == 0) {
+      part[w][c] = a;
+      part[w][LOC_DIMS + c] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nd) {
+    const int c = threadIdx.x;
+    const float a = fminf(fminf(part[0][c], part[1][c]), fminf(part[2][c], part[3][c]));
+    const float b = fmaxf(fmaxf(part[0][LOC_DIMS + c], part[1][LOC_DIMS + c]),
+                          fmaxf(part[2][LOC_DIMS + c], part[3][LOC_DIMS + c]));
+    if (a <= b) {
+      atomicMin(&rng[c], f_ord(a));
+      atomicMax(&rng[LOC_DIMS + c], f_ord(b));
+    }
+  }
+}
+
+// key[i] = the Morton key of point i (0 for non-finite coordinates), and its
+// count in hist.
+__global__ __launch_bounds__(256) void loc_key_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                      const uint32_t* __restrict__ rng, uint16_t* __restrict__ key,
+                                                      int* __restrict__ hist) {
+  const int nd = d < LOC_DIMS ? d : LOC_DIMS;
+  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    uint32_t q[LOC_DIMS] = {0u, 0u, 0u};
+#pragma unroll
+    for (int c = 0; c < LOC_DIMS; ++c) {
+      if (c >= nd || rng[c] > rng[LOC_DIMS + c]) continue;  // no finite value at all
+      const float lo = ord_f(rng[c]), hi = ord_f(rng[LOC_DIMS + c]);
+      const float v = X[i * d + c];
+      const float cells = float(1u << LOC_BITS[c]);
+      const float t = hi > lo ? (v - lo) / (hi - lo) * cells : 0.0f;
+      q[c] = (isfinite(t) && t > 0.0f) ? (t < cells ? uint32_t(t) : (1u << LOC_BITS[c]) - 1u) : 0u;
+    }
+    // interleave from the top: q0 bit 5, then (q0, q1, q2) bits 4 .. 0
+    uint32_t k = (q[0] >> 5) & 1u;
+#pragma unroll
+    for (int b = 4; b >= 0; --b) k = (k << 3) | (((q[0] >> b) & 1u) << 2) | (((q[1] >> b) & 1u) << 1) | ((q[2] >> b) & 1u);
+    key[i] = uint16_t(k);
+    atomicAdd(&hist[k], 1);
+  }
+}
+
+// perm[off[key] + rank among the points of that key] = i.
+__global__ __launch_bounds__(256) void loc_scatter_kernel(const uint16_t* __restrict__ key, int64_t n,
+                                                          const int64_t* __restrict__ off, int* __restrict__ cur,
+                                                          int32_t* __restrict__ perm) {
+  for (int64_t i = gtid(); i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const uint32_t k = key[i];
+    perm[off[k] + atomicAdd(&cur[k], 1)] = int32_t(i);
+  }
+}
+
+// One wave per position p of the locality order, for point perm[p].
+// Query row:      [x~ (d), nh, nm, nl, 1, 1, 1, 0 ...]
+// candidate row:  [-2 x~ (d), 1, 1, 1, nh, nm, nl, 0 ...]
 // so that <query_i, candidate_j> = |x~_i|^2 + |x~_j|^2 - 2 <x~_i, x~_j>, the
 // squared distance of the rounded points; |x~|^2 (FP32) is carried as the
 // sum nh + nm + nl of three bf16 parts.  Candidate row n is a point at
 // infinite distance from every query ([0 ..., inf at d + 3, 0 ...]): the
 // tiles past the last point are filled with it, so they need no bounds test.
 __global__ __launch_bounds__(256) void bf16_prep_kernel(const float* __restrict__ X, int64_t n, int d,
-                                                        uint16_t* __restrict__ Xq, uint16_t* __restrict__ Xc) {
+                                                        const int32_t* __restrict__ perm, uint16_t* __restrict__ Xq,
+                                                        uint16_t* __restrict__ Xc) {
   const int lane = lane_id();
   const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (row > n) return;
@@ -322,8 +433,9 @@ __global__ __launch_bounds__(256) void bf16_prep_kernel(const float* __restrict_
     Xc[row * 64 + lane] = lane == d + 3 ? BF16_INF : uint16_t(0);
     return;
   }
+  const int64_t src = perm[row];
   const bool has = lane < d;
-  const uint16_t h = has ? bf16_rne(X[row * d + lane]) : uint16_t(0);
+  const uint16_t h = has ? bf16_rne(X[src * d + lane]) : uint16_t(0);
   const float xr = bf16_to_f(h);
   const float nrm = wave_sum(xr * xr);
   const uint16_t nh = bf16_rne(nrm);
@@ -358,7 +470,11 @@ constexpr int B_TJ = 64;  // candidates per LDS tile
 // of 16 consecutive rows hit distinct banks.
 __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r & 7)); }
 
-// Block = 4 waves x 64 queries.  Lane l works on queries 16 t + (l % 16),
+// Block = 4 waves x 64 queries, positions of the locality order (Xq, Xc and
+// the buffers are in that order; perm maps a position to its point, which
+// is what keys and outputs name).  The candidate tiles are swept cyclically
+// from two tiles before the block's first query, so the block's own
+// neighbourhood comes first.  Lane l works on queries 16 t + (l % 16),
 // t = 0..3, of its wave and, per 16-candidate subtile, on candidates
 // 4 (l / 16) .. + 3 (the MFMA C layout).  A query's threshold and buffer
 // count are held (identically) by its four lanes.  Four blocks fit a CU
@@ -368,8 +484,8 @@ __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r 
 // queries in one round.
 template <int EPL>
 __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
-                                                       int64_t n, int ncand, uint64_t* __restrict__ bufs,
-                                                       int32_t* __restrict__ cand) {
+                                                       const int32_t* __restrict__ perm, int64_t n, int ncand,
+                                                       uint64_t* __restrict__ bufs, int32_t* __restrict__ cand) {
   constexpr int CAP = 64 * EPL;
   __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
   __shared__ uint32_t hist_s[4][256];   // per-wave radix-select histograms
@@ -409,13 +525,21 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
       __builtin_amdgcn_global_load_lds(src, dst + (u & ~63), 16, 0, 0);
     }
   };
-  load_tile(0, tile[0]);
+  const int64_t ntiles = (n + B_TJ - 1) / B_TJ;
+  int64_t t0 = (qblock / B_TJ - 2) % ntiles;
+  if (t0 < 0) t0 += ntiles;
+  auto tile_c0 = [&](int64_t it) -> int64_t {
+    const int64_t ti = t0 + it;
+    return (ti < ntiles ? ti : ti - ntiles) * B_TJ;
+  };
+  load_tile(tile_c0(0), tile[0]);
   int buf = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += B_TJ) {
+  for (int64_t it = 0; it < ntiles; ++it) {
+    const int64_t c0 = tile_c0(it);
     __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the tile has landed
     __syncthreads();                // ... and every wave's; the other buffer is free
     // fetch the next tile while this one is consumed
-    if (c0 + B_TJ < n) load_tile(c0 + B_TJ, tile[buf ^ 1]);
+    if (it + 1 < ntiles) load_tile(tile_c0(it + 1), tile[buf ^ 1]);
     const uint4* tl = tile[buf];
     // tiles that hold some of this block's queries exclude the self pairs;
     // the others need only the threshold test
@@ -437,8 +561,7 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
         bool any = false;
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) any |= acc[t][r] <= tau[t];
+          any |= fminf(fminf(acc[t][0], acc[t][1]), fminf(acc[t][2], acc[t][3])) <= tau[t];
         if (__ballot(any)) {
           const int64_t jb = c0 + sub * 16 + 4 * g4;
 #pragma unroll
@@ -467,7 +590,9 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
             const int lo_off = q16 * CAP;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (p[r]) tbuf[lo_off + pos++] = make_key(fmaxf(acc[t][r], 0.0f), int32_t(jb + r));
+              // (a candidate past the last point is at +inf and never passes;
+              // the clamp only keeps the index read in bounds regardless)
+              if (p[r]) tbuf[lo_off + pos++] = make_key(fmaxf(acc[t][r], 0.0f), perm[jb + r < n ? jb + r : n - 1]);
           }
         }
       }
@@ -500,22 +625,26 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
     if (qi >= n) break;
     const int t = r >> 4;
     const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], r & 15);
-    emit_row<EPL>(bufs + qi * CAP, c, ncand, cand + qi * ncand, nullptr);
+    emit_row<EPL>(bufs + qi * CAP, c, ncand, cand + int64_t(perm[qi]) * ncand, nullptr);
   }
 }
 
 // Re-rank: one wave per row; FP32 direct differences (same arithmetic as the
 // FP32 path: squares accumulated in dimension order) of the row's
-// candidates, sorted by (d, j); best k written.  The query row is read with
-// uniform (scalar) loads; each lane issues all loads of a candidate row
-// before the arithmetic (d <= DMAX).
+// candidates, sorted by (d, j); best k written.  Rows are taken in the
+// locality order (wave w re-ranks row perm[w]), so the waves resident at one
+// time gather overlapping candidate rows from the caches.  The query row is
+// read with uniform (scalar) loads; each lane issues all loads of a
+// candidate row before the arithmetic (d <= DMAX).
 template <int DMAX>
 __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X, int64_t n, int d,
-                                                     const int32_t* __restrict__ cand, int ncand, int k,
-                                                     int32_t* __restrict__ out_idx, float* __restrict__ out_d2) {
+                                                     const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
+                                                     int ncand, int k, int32_t* __restrict__ out_idx,
+                                                     float* __restrict__ out_d2) {
   const int lane = lane_id();
-  const int64_t row = int64_t(__builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6)));
-  if (row >= n) return;
+  const int64_t pos = int64_t(__builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6)));
+  if (pos >= n) return;
+  const int64_t row = int64_t(__builtin_amdgcn_readfirstlane(perm[pos]));
   float xi[DMAX];
 #pragma unroll
   for (int c = 0; c < DMAX; ++c) xi[c] = c < d ? X[row * d + c] : 0.0f;
@@ -558,27 +687,33 @@ __global__ __launch_bounds__(256) void count_nonfinite_kernel(const float* __res
                                                               unsigned long long* __restrict__ out) {
   int c = 0;
   for (int64_t i = gtid(); i < count; i += int64_t(gridDim.x) * blockDim.x) c += !isfinite(a[i]);
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
+  c = wave_sum_i(c);
   if (__lane_id() == 0 && c) atomicAdd(out, static_cast<unsigned long long>(c));
 }
 
 struct KnnLayout {
   int epl;
-  size_t o_buf, o_xq, o_xc, o_cand, bytes;
+  size_t o_buf, o_xq, o_xc, o_cand, o_perm, o_key, o_rng, o_hist, o_cur, o_off, o_bsum, bytes;
   static KnnLayout make(int64_t n, int k, int precision, int ncand) {
     KnnLayout L;
     Carve c;
     if (precision == TSNE_KNN_FP32) {
       L.epl = 8;  // capacity 512: room for 384 appends between compactions
       L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * size_t(64 * L.epl));
-      L.o_xq = L.o_xc = L.o_cand = 0;
+      L.o_xq = L.o_xc = L.o_cand = L.o_perm = L.o_key = L.o_rng = L.o_hist = L.o_cur = L.o_off = L.o_bsum = 0;
     } else {
       L.epl = 8;  // capacity 512, headroom 64 per tile
       L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * 512);
       L.o_xq = c.take(sizeof(uint16_t) * size_t(n) * 64);
       L.o_xc = c.take(sizeof(uint16_t) * size_t(n + 1) * 64);  // + the infinite row
       L.o_cand = c.take(sizeof(int32_t) * size_t(n) * size_t(ncand));
+      L.o_perm = c.take(sizeof(int32_t) * size_t(n));
+      L.o_key = c.take(sizeof(uint16_t) * size_t(n));
+      L.o_rng = c.take(sizeof(uint32_t) * 2 * LOC_DIMS);
+      L.o_hist = c.take(sizeof(int) * LOC_BINS);
+      L.o_cur = c.take(sizeof(int) * LOC_BINS);
+      L.o_off = c.take(sizeof(int64_t) * (LOC_BINS + 1));
+      L.o_bsum = c.take(sizeof(int64_t) * (size_t(ceil_div(LOC_BINS + 1, SCAN_CHUNK)) + 1));
     }
     L.bytes = c.off;
     return L;
@@ -625,13 +760,35 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   uint16_t* Xq = reinterpret_cast<uint16_t*>(ws + L.o_xq);
   uint16_t* Xc = reinterpret_cast<uint16_t*>(ws + L.o_xc);
   int32_t* cand = reinterpret_cast<int32_t*>(ws + L.o_cand);
-  hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(n + 1, 4))), dim3(256), 0, s, X, n, d, Xq, Xc);
+  // locality order: key range, keys and their counts, offsets, scatter
+  uint32_t* rng = reinterpret_cast<uint32_t*>(ws + L.o_rng);
+  uint16_t* key = reinterpret_cast<uint16_t*>(ws + L.o_key);
+  int* hist = reinterpret_cast<int*>(ws + L.o_hist);
+  int* cur = reinterpret_cast<int*>(ws + L.o_cur);
+  int64_t* off = reinterpret_cast<int64_t*>(ws + L.o_off);
+  int64_t* bsum = reinterpret_cast<int64_t*>(ws + L.o_bsum);
+  int32_t* perm = reinterpret_cast<int32_t*>(ws + L.o_perm);
+  if ((rc = launch_fill<uint32_t>(rng, LOC_DIMS, ~0u, s))) return rc;
+  if ((rc = launch_fill<uint32_t>(rng + LOC_DIMS, LOC_DIMS, 0u, s))) return rc;
+  if ((rc = launch_fill<int>(hist, LOC_BINS, 0, s))) return rc;
+  if ((rc = launch_fill<int>(cur, LOC_BINS, 0, s))) return rc;
+  const dim3 lgrid(unsigned(ceil_div(n, 256) < 2048 ? ceil_div(n, 256) : 2048));
+  hipLaunchKernelGGL(loc_range_kernel, dim3(unsigned(ceil_div(n, 256) < 256 ? ceil_div(n, 256) : 256)), dim3(256), 0,
+                     s, X, n, d, rng);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(loc_key_kernel, lgrid, dim3(256), 0, s, X, n, d, rng, key, hist);
+  TSNE_CHECK_LAUNCH();
+  if ((rc = exclusive_scan<int>(hist, LOC_BINS, off, bsum, s))) return rc;
+  hipLaunchKernelGGL(loc_scatter_kernel, lgrid, dim3(256), 0, s, key, n, off, cur, perm);
+  TSNE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(n + 1, 4))), dim3(256), 0, s, X, n, d, perm, Xq, Xc);
   TSNE_CHECK_LAUNCH();
   hipLaunchKernelGGL(knn_bf16_kernel<8>, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
-                     reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), n, n_cand, bufs, cand);
+                     reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), perm, n, n_cand, bufs,
+                     cand);
   TSNE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(rerank_kernel<TSNE_MAX_D_BF16>, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, cand,
-                     n_cand, k, nbr_idx, nbr_d2);
+  hipLaunchKernelGGL(rerank_kernel<TSNE_MAX_D_BF16>, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, perm,
+                     cand, n_cand, k, nbr_idx, nbr_d2);
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
 }
