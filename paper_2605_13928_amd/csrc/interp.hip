@@ -695,6 +695,10 @@ extern "C" int tsne_kl_grad_fft(const float* Y, int64_t n, const int64_t* row_pt
   TSNE_CHECK_LAUNCH();
   if ((rc = fi_fft2(Cg, L.plane, 2, par, max_fft, 1.0, s))) return rc;
   if ((rc = fi_points(n_interp, false, Y2, n, par, off, order, choff, L.nbox, G, Cg, L.plane, R, Zb, s))) return rc;
+  // the attraction takes the rows in box order (a spatial order of Y: rows
+  // that share P-neighbours run together, so their y_j gathers hit L2); the
+  // order within a box follows the scatter's atomics, so a requested KL, whose
+  // per-block sums would follow it, takes the rows in index order instead
   return finalize_csr_launch(Y, n, row_ptr, col, val, exaggeration, reinterpret_cast<const float*>(R), Zb, FI_GRID,
-                             grad, Z, kl, klp, nf, s);
+                             grad, Z, kl, klp, nf, s, kl ? nullptr : order);
 }

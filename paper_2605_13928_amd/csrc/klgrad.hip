@@ -14,14 +14,19 @@
 
 namespace tsne {
 
-// Finalize, 16 rows per block.
+// Finalize, 16 rows per block: rows 16 b .. 16 b + 15, or with `rows` the
+// rows rows[16 c .. 16 c + 15] (a permutation of 0 .. n - 1: a spatial order
+// makes the y_j gathers of the rows resident together overlap in L2), with c
+// the block's place in the eighth of the blocks on its XCD.
 // Attraction A_i = sum_{e in row i} p_e w_e (y_i - y_j), entry-parallel: the
-// block's CSR entries are dealt to all 256 threads in chunks of FIN_CHUNK
-// (thread t takes entries c0 + t + 256 m, m < FIN_EPT), so a hub row with
-// thousands of entries costs the block no more dependent trips than a short
-// one: every thread issues its column/value loads, then its y_j gathers,
-// then writes p w (y_i - y_j) to LDS, and the 16 lanes of group g add row
-// g's contributions in entry order (strided by 16, then a DPP reduction).
+// block's CSR entries, numbered flat over its rows, are dealt to all 256
+// threads in chunks of FIN_CHUNK (thread t takes flat entries c0 + t + 256 m,
+// m < FIN_EPT), so a hub row with thousands of entries costs the block no
+// more dependent trips than a short one: every thread issues its
+// column/value loads, then its y_j gathers, then writes p w (y_i - y_j) to
+// LDS, and lane l of the 16 of group g adds row g's entries l, l + 16, ...
+// (counted from the row's first entry, so a row's sum does not depend on
+// which rows share its block), then a DPP reduction.
 // Optional per-block sums of p ln p, p ln q (q = 1/w) and p for the KL.
 // Repulsion partials: thread (g, sl) adds slices g, g + 16, ... of row
 // r0 + sl in FP64; the 16 slice sums are combined in a fixed order.  The
@@ -45,22 +50,44 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     const float* __restrict__ val, float alpha, const float2* __restrict__ Rpart, const float* __restrict__ Zrowpart,
     const float2* __restrict__ Apart, int64_t ns, bool grouped, const double* __restrict__ Zblock, int64_t nZ,
     float2* __restrict__ grad, double* __restrict__ Zrow, double* __restrict__ Z_out, double* __restrict__ klpart,
-    FusedStep st, unsigned long long* __restrict__ nonfinite) {
+    FusedStep st, unsigned long long* __restrict__ nonfinite, const int32_t* __restrict__ rows) {
   constexpr int NPR = ATTP ? 5 : 3;  // per-thread sums: R x, R y, Z_row (, A x, A y)
   __shared__ float2 contrib[ATTP ? 1 : FIN_CHUNK];
-  __shared__ int64_t rps[FIN_ROWS + 1];
+  __shared__ int64_t rp0[FIN_ROWS];      // first CSR entry of each row of the block
+  __shared__ int64_t cum[FIN_ROWS + 1];  // flat offsets of the rows' entries
   __shared__ float2 yrow[FIN_ROWS];
   __shared__ double red[4];
   __shared__ double pr[16][FIN_ROWS][NPR];
   __shared__ float2 att[FIN_ROWS];
   const int tid = threadIdx.x;
   const int g = tid >> 4, sl = tid & 15;
-  const int64_t r0 = int64_t(blockIdx.x) * FIN_ROWS;
-  const int64_t prow = r0 + sl;  // partial-sum row of this thread
+  // With a row order, workgroups (dealt round-robin over the 8 XCDs) take
+  // their group of 16 from the contiguous eighth of the order that belongs
+  // to their XCD, so each XCD's L2 holds the y_j of one compact region.
+  int64_t blk = blockIdx.x;
+  if (rows) {
+    const int64_t nb = gridDim.x, x = blk % 8;
+    int64_t base = 0;
+    for (int64_t u = 0; u < x; ++u) base += (nb - u + 7) / 8;  // blocks of the XCDs before
+    blk = base + blk / 8;
+  }
+  const int64_t r0 = blk * FIN_ROWS;
+  // the block's row of local index q (n past the last one)
+  auto row_of = [&](int q) -> int64_t {
+    const int64_t p = r0 + q;
+    return p < n ? (rows ? int64_t(rows[p]) : p) : n;
+  };
+  const int64_t prow = row_of(sl);  // partial-sum row of this thread
+  const int64_t myrow = tid < FIN_ROWS ? row_of(tid) : n;
 
   // --- loads with no dependences -----------------------------------------
-  if (tid <= FIN_ROWS) rps[tid] = row_ptr[r0 + tid < n ? r0 + tid : n];
-  if (tid < FIN_ROWS) yrow[tid] = r0 + tid < n ? Y[r0 + tid] : make_float2(0.0f, 0.0f);
+  int64_t len = 0;
+  if (tid < FIN_ROWS) {
+    const int64_t a = myrow < n ? row_ptr[myrow] : 0, b = myrow < n ? row_ptr[myrow + 1] : 0;
+    rp0[tid] = a;
+    len = b - a;
+    yrow[tid] = myrow < n ? Y[myrow] : make_float2(0.0f, 0.0f);
+  }
   float2 rpv[FIN_PRE], apv[FIN_PRE];
 #pragma unroll
   for (int u = 0; u < FIN_PRE; ++u) {
@@ -71,30 +98,45 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
   }
   // the stepped rows' state (in flight while the partials are summed)
   float2 sy = make_float2(0.0f, 0.0f), su = sy, sg = sy;
-  if (STEP && tid < FIN_ROWS && r0 + tid < n) {
-    sy = Y[r0 + tid];
-    su = st.U[r0 + tid];
-    sg = st.G[r0 + tid];
+  if (STEP && myrow < n) {
+    sy = Y[myrow];
+    su = st.U[myrow];
+    sg = st.G[myrow];
   }
   const double zt = zblock_thread_sum(Zblock, nZ);
   if (!STEP && nonfinite && tid < 64) {  // wave 0 covers the block's rows
-    const float2 y = (tid < FIN_ROWS && r0 + tid < n) ? Y[r0 + tid] : make_float2(0.0f, 0.0f);
+    const float2 y = myrow < n ? Y[myrow] : make_float2(0.0f, 0.0f);
     const int bad = __popcll(__ballot(!isfinite(y.x))) + __popcll(__ballot(!isfinite(y.y)));
     if (tid == 0 && bad) atomicAdd(nonfinite, static_cast<unsigned long long>(bad));
+  }
+  if (tid < 64) {  // flat offsets: inclusive sum of the 16 lengths in DPP row 0
+    int64_t c = len;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int64_t u = int64_t(__shfl_up(uint64_t(c), o, 16));
+      if ((tid & 15) >= o) c += u;
+    }
+    if (tid < FIN_ROWS) cum[tid + 1] = c;
+    if (tid == 0) cum[0] = 0;
   }
   __syncthreads();
 
   // --- attraction, entry-parallel -----------------------------------------
-  const int64_t E0 = rps[0], E1 = rps[FIN_ROWS];
-  const int64_t ga = rps[g], gb = rps[g + 1];
+  const int64_t F = cum[FIN_ROWS];
+  const int64_t ga = cum[g], gb = cum[g + 1];
   float ax = 0.0f, ay = 0.0f, plp = 0.0f, plq = 0.0f, ps = 0.0f;
-  for (int64_t c0 = E0; !ATTP && c0 < E1; c0 += FIN_CHUNK) {
+  for (int64_t c0 = 0; !ATTP && c0 < F; c0 += FIN_CHUNK) {
     int32_t jj[FIN_EPT];
     float pp[FIN_EPT];
+    int rr[FIN_EPT];
+    int r = 0;  // row of the flat entry (a thread's entries are increasing)
 #pragma unroll
     for (int m = 0; m < FIN_EPT; ++m) {
-      const int64_t e = c0 + tid + 256 * m;
-      const bool ok = e < E1;
+      const int64_t f = c0 + tid + 256 * m;
+      const bool ok = f < F;
+      while (r < FIN_ROWS - 1 && cum[r + 1] <= f) ++r;
+      rr[m] = r;
+      const int64_t e = rp0[r] + (f - cum[r]);
       // read once: non-temporal, so the stream of entries does not evict the
       // gathered rows of Y from L2
       jj[m] = ok ? __builtin_nontemporal_load(col + e) : 0;
@@ -110,12 +152,9 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     float2 yj[FIN_EPT];
 #pragma unroll
     for (int m = 0; m < FIN_EPT; ++m) yj[m] = Y[jj[m]];
-    int r = 0;  // row of the entry (entries of a thread are increasing)
 #pragma unroll
     for (int m = 0; m < FIN_EPT; ++m) {
-      const int64_t e = c0 + tid + 256 * m;
-      while (r < FIN_ROWS - 1 && rps[r + 1] <= e) ++r;
-      const float2 yi = yrow[r];
+      const float2 yi = yrow[rr[m]];
       const float dx = yi.x - yj[m].x, dy = yi.y - yj[m].y;
       const float q = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f));
       const float pw = pp[m] * __builtin_amdgcn_rcpf(q);
@@ -129,8 +168,10 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     __syncthreads();
     const int64_t lo = ga > c0 ? ga : c0;
     const int64_t hi = gb < c0 + FIN_CHUNK ? gb : c0 + FIN_CHUNK;
-    for (int64_t e = lo + sl; e < hi; e += 16) {
-      const float2 c = contrib[e - c0];
+    int64_t f = ga + sl;  // this lane's entries of row g: ga + sl + 16 m
+    if (f < lo) f += (lo - f + 15) / 16 * 16;
+    for (; f < hi; f += 16) {
+      const float2 c = contrib[f - c0];
       ax += c.x;
       ay += c.y;
     }
@@ -194,7 +235,7 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
   if (sl == 0) att[g] = make_float2(ax, ay);
   const double Z = block_sum_d(zt, red);  // its barriers also publish pr and att
   if (blockIdx.x == 0 && tid == 0 && Z_out) *Z_out = Z;
-  if (tid < FIN_ROWS && r0 + tid < n) {
+  if (myrow < n) {
     double Rx = 0.0, Ry = 0.0, Zr = 0.0, Ax = 0.0, Ay = 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -212,7 +253,7 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
     }
     const float2 gi = make_float2(float(4.0 * (double(alpha) * Ax - Rx / Z)),
                                   float(4.0 * (double(alpha) * Ay - Ry / Z)));
-    const int64_t i = r0 + tid;
+    const int64_t i = myrow;
     if (STEP) {
       step_coord(sy.x, su.x, sg.x, gi.x, st.lr, st.mom, st.inc, st.dec, st.mn);
       step_coord(sy.y, su.y, sg.y, gi.y, st.lr, st.mom, st.inc, st.dec, st.mn);
@@ -262,14 +303,16 @@ size_t finalize_kl_bytes(int64_t n) { return sizeof(double) * 3 * size_t(ceil_di
 
 int finalize_csr_launch(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                         float alpha, const float* R, const double* Zblock, int64_t nZ, float* grad, double* Z,
-                        double* kl, double* klpart, unsigned long long* nonfinite, hipStream_t s) {
+                        double* kl, double* klpart, unsigned long long* nonfinite, hipStream_t s,
+                        const int32_t* rows) {
   const int64_t nfin = ceil_div(n, FIN_ROWS);
   double* kp = kl ? klpart : nullptr;
   hipLaunchKernelGGL((finalize_tsne_kernel<false, false>), dim3(unsigned(nfin)), dim3(256), 0, s,
                      reinterpret_cast<const float2*>(Y), n, row_ptr, col, val, alpha,
                      reinterpret_cast<const float2*>(R), static_cast<const float*>(nullptr),
                      static_cast<const float2*>(nullptr), int64_t(1), false, Zblock, nZ,
-                     reinterpret_cast<float2*>(grad), static_cast<double*>(nullptr), Z, kp, FusedStep{}, nonfinite);
+                     reinterpret_cast<float2*>(grad), static_cast<double*>(nullptr), Z, kp, FusedStep{}, nonfinite,
+                     rows);
   TSNE_CHECK_LAUNCH();
   if (kl) {
     hipLaunchKernelGGL(kl_reduce_kernel, dim3(1), dim3(256), 0, s, kp, nfin, Zblock, nZ, kl);
@@ -466,7 +509,8 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
   const FusedStep st = step ? *step : FusedStep{};
 #define TSNE_FIN(STEP, A, GR, KLP, NF)                                                                      \
   hipLaunchKernelGGL((finalize_tsne_kernel<STEP, A>), fgrid, block, 0, s, Y2, n, row_ptr, col, val, alpha, R2, \
-                     Zrowpart, Apart, g.ns, grp, Zblock, g.nwg, GR, Zrow, Z, KLP, st, NF)
+                     Zrowpart, Apart, g.ns, grp, Zblock, g.nwg, GR, Zrow, Z, KLP, st, NF,                    \
+                     static_cast<const int32_t*>(nullptr))
   if (fused) {
     if (step) TSNE_FIN(true, true, nullptr, nullptr, nonfinite);
     else TSNE_FIN(false, true, gr, nullptr, nonfinite);

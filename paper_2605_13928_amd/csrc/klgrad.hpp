@@ -69,10 +69,14 @@ int klgrad_launch(const KlGradPlan& L, char* ws, const float* Y, int64_t n, cons
 // block partials (Z = their sum, in index order) were computed elsewhere:
 // attraction over the CSR rows, g = 4 (alpha A - R / Z), optional Z and KL
 // outputs.  klpart: finalize_kl_bytes(n) of workspace (used when kl).
+// rows (nullable): a permutation of the rows, the order the blocks take them
+// in (a row's result does not depend on it; the KL's per-block sums do, so
+// pass none when kl is requested and the order is not reproducible).
 size_t finalize_kl_bytes(int64_t n);
 int finalize_csr_launch(const float* Y, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val,
                         float alpha, const float* R, const double* Zblock, int64_t nZ, float* grad, double* Z,
-                        double* kl, double* klpart, unsigned long long* nonfinite, hipStream_t s);
+                        double* kl, double* klpart, unsigned long long* nonfinite, hipStream_t s,
+                        const int32_t* rows = nullptr);
 
 // Enqueue one optimiser step (arguments as tsne_step, validated).
 int step_launch(float* Y, float* update, float* gains, const float* grad, int64_t n, float lr, float momentum,
