@@ -71,6 +71,18 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // 2^31-safe linear thread index.
 __device__ __forceinline__ int64_t gtid() { return int64_t(blockIdx.x) * blockDim.x + threadIdx.x; }
 
+// Workgroups are dealt to the 8 XCDs of an MI355X round-robin by index.
+// xcd_block() renumbers them so that the ones on XCD x get consecutive
+// numbers (the x-th eighth of 0 .. gridDim.x - 1, in launch order): work
+// items that are near each other in a locality order then share the L2 of
+// one XCD.  A bijection of [0, gridDim.x).
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x, x = b % 8;
+  int64_t base = 0;
+  for (int64_t u = 0; u < x; ++u) base += (nb - u + 7) / 8;  // blocks on the XCDs before
+  return base + b / 8;
+}
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // DPP move within a row of 16 lanes (row_ror:n is 0x120 + n).

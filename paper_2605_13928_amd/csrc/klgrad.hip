@@ -64,14 +64,7 @@ __global__ __launch_bounds__(256) void finalize_tsne_kernel(
   // With a row order, workgroups (dealt round-robin over the 8 XCDs) take
   // their group of 16 from the contiguous eighth of the order that belongs
   // to their XCD, so each XCD's L2 holds the y_j of one compact region.
-  int64_t blk = blockIdx.x;
-  if (rows) {
-    const int64_t nb = gridDim.x, x = blk % 8;
-    int64_t base = 0;
-    for (int64_t u = 0; u < x; ++u) base += (nb - u + 7) / 8;  // blocks of the XCDs before
-    blk = base + blk / 8;
-  }
-  const int64_t r0 = blk * FIN_ROWS;
+  const int64_t r0 = (rows ? xcd_block() : int64_t(blockIdx.x)) * FIN_ROWS;
   // the block's row of local index q (n past the last one)
   auto row_of = [&](int q) -> int64_t {
     const int64_t p = r0 + q;
