@@ -63,6 +63,23 @@ def test_fft_grad_deterministic(dev):
     assert torch.equal(a, b) and torch.equal(Za, Zb)
 
 
+def test_fft_grad_same_bits_in_either_row_order(dev):
+    """The attraction pass takes the rows in box order unless the KL is asked
+    for (then in index order); a row's sum must not depend on which rows
+    share its block, so the gradient and Z come out bit for bit the same.
+    With k = 90 a block's 16 rows hold about 2,900 entries, so rows straddle
+    the 2,048-entry chunks in both orders."""
+    say("fft grad: box order vs index order")
+    n = 20_000
+    _, _, _, S = random_graph_P(n, 90, 30.0, 3)
+    P = sparse_to_dev(widen(S), dev)
+    Y = to_dev(synth.random_embedding(n, 15.0, 4101), dev)
+    a, Za, _ = api.kl_grad_fft(Y, P, 1.0, want_Z=True)
+    b, Zb, klb = api.kl_grad_fft(Y, P, 1.0, want_Z=True, want_kl=True)
+    assert torch.equal(a, b) and torch.equal(Za, Zb)
+    assert torch.isfinite(klb).all()
+
+
 def test_fft_grad_close_to_exact_c2(dev):
     # the approximation against the exact gradient at 20k points: about 1e-2
     # relative at box side 1 (the method's default), third order below it
