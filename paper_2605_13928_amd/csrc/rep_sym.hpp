@@ -22,7 +22,12 @@
 // (both staged in LDS): i-side sums stay in registers; after every tile the
 // j-side sums are reduce-scattered over the 8 lanes that share a j-group
 // (gfx950 v_permlane32_swap / v_permlane16_swap, then a DPP row rotation)
-// and added to the wave's own LDS accumulator.  At the end of a job the
+// and added to the wave's own LDS accumulator.  In the off-diagonal jobs
+// of the launches without per-row Z, a wave takes its PF = S / 256
+// subblocks together instead, the j-tiles in the outer loop: the PF tiles
+// of one j-tile add into the same j-side registers, so one reduce-scatter
+// serves PF tiles (at S = 1024 that takes the per-pair instruction count
+// from about 11.9 to 11.3).  At the end of a job the
 // workgroup adds the 4 wave accumulators in a fixed order and writes one
 // partial per point and opposite superblock: slice t for i in s and slice
 // s for j in t (for s == t both sides land in the same slot and are added
@@ -197,7 +202,10 @@ __device__ __forceinline__ int64_t sym_sched(int64_t pos, int64_t ns, bool last_
 
 // One 64 x 64 wave tile.  DIAG: i and j blocks coincide; all ordered pairs
 // go to the i side, self pairs masked, Z weight 1 (else 2, via the caller).
-template <bool DIAG, bool ZROW>
+// CLEARJ: start the j-side sums at zero (else add to them).  ROWFENCE:
+// keep each row's 8 pairs together in the schedule (bounds the registers
+// that hold differences in flight).
+template <bool DIAG, bool ZROW, bool CLEARJ = true, bool ROWFENCE = false>
 __device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)[8], const float4 (&pjv)[4],
                                          float (&rix)[8], float (&riy)[8], float (&zi)[8], float (&rj)[16],
                                          float (&zj)[8], float& z, bool same_group) {
@@ -210,11 +218,13 @@ __device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)
     xj[c + 1] = v.z;
     yj[c + 1] = v.w;
   }
+  if (CLEARJ) {
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    rj[c] = 0.0f;
-    rj[8 + c] = 0.0f;
-    if (ZROW) zj[c] = 0.0f;
+    for (int c = 0; c < 8; ++c) {
+      rj[c] = 0.0f;
+      rj[8 + c] = 0.0f;
+      if (ZROW) zj[c] = 0.0f;
+    }
   }
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
@@ -235,6 +245,7 @@ __device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)
         if (ZROW) zj[c] += w;
       }
     }
+    if (ROWFENCE) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -272,6 +283,10 @@ __global__ __launch_bounds__(256, 2) void rep_sym_kernel(const float2* __restric
   float2* jpts = ipts + S;
   float* iacc = lds + 4 * S;
   float* jacc = iacc + NC * S;
+  // subblocks per wave swept together in off-diagonal jobs, and the tiles
+  // between two folds of their i-side sums into FP64 (8 j-points per tile)
+  constexpr int GS = ZROW ? 1 : PF;
+  constexpr int GS_FOLD = 16;
   // attraction sums of the job in 64-bit fixed point: i x, i y, j x, j y.
   // Small superblocks have room for a separate array; the largest reuse the
   // j accumulators before the pair tiles need them (ATT_SEP false).
@@ -414,6 +429,92 @@ __global__ __launch_bounds__(256, 2) void rep_sym_kernel(const float2* __restric
     // (the result is the same bits as with them)
     const int ni_end = int(min(int64_t(nsub), (n - s * S + 63) / 64));
     const int nj_end = int(min(int64_t(nsub), (n - t * S + 63) / 64));
+    if (GS > 1 && !diag_sb) {
+      // Off-diagonal job (superblock s is full): the wave's GS subblocks
+      // us = w + 4 k are swept together, the j-tiles in the outer loop, so
+      // one reduce-scatter carries the j-side sums of GS 64 x 64 tiles.
+      float xi[GS][8], yi[GS][8], rix[GS][8], riy[GS][8];
+      double di[GS][2];
+#pragma unroll
+      for (int k = 0; k < GS; ++k) {
+        const int us = w + SYM_WAVES * k;
+#pragma unroll
+        for (int r = 0; r < 8; r += 2) {
+          const float4 v = *reinterpret_cast<const float4*>(ipts + 64 * us + 8 * a + r);
+          xi[k][r] = v.x;
+          yi[k][r] = v.y;
+          xi[k][r + 1] = v.z;
+          yi[k][r + 1] = v.w;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) rix[k][r] = riy[k][r] = 0.0f;
+        di[k][0] = di[k][1] = 0.0;
+      }
+      auto fold_all = [&]() {
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          float vi[16];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            vi[r] = rix[k][r];
+            vi[8 + r] = riy[k][r];
+            rix[k][r] = riy[k][r] = 0.0f;
+          }
+          float o0, o1;
+          rs16_lo(vi, o0, o1);
+          di[k][0] += double(o0);
+          di[k][1] += double(o1);
+        }
+      };
+      const int comp = lane >> 5;
+      const int c0 = 2 * ((lane >> 3) & 1) + 4 * ((lane >> 4) & 1);
+      int since_fold = 0;
+      for (int v = 0; v < nj_end; ++v) {
+        float4 jc[4];
+        {
+          const float4* p = reinterpret_cast<const float4*>(jpts + 64 * v + 8 * b);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) jc[c] = p[c];
+        }
+        float2* dst = reinterpret_cast<float2*>(myj + comp * S + 64 * v + 8 * b + c0);
+        float2 cur = *dst;
+        float rj[16], zj[8], zi[8];
+        float z = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) rj[c] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          sym_tile<false, false, false, true>(xi[k], yi[k], jc, rix[k], riy[k], zi, rj, zj, z, false);
+          // keep the scheduler from interleaving the GS tiles (their live
+          // differences would not fit the register file)
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        // z complete here: otherwise its chain of adds is sunk below the
+        // fold and every w of the tiles stays live until then
+        asm volatile("" : "+v"(z));
+        zsum += 2.0 * double(z);
+        float o0, o1;
+        rs16_hi(rj, o0, o1);
+        cur.x += o0;
+        cur.y += o1;
+        *dst = cur;
+        if (++since_fold == GS_FOLD) {
+          since_fold = 0;
+          fold_all();
+        }
+      }
+      if (since_fold) fold_all();
+      {
+        const int comp = (lane >> 2) & 1;
+        const int c0 = 2 * (lane & 1) + 4 * ((lane >> 1) & 1);
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          float* dst = iacc + comp * S + 64 * (w + SYM_WAVES * k) + 8 * a + c0;
+          dst[0] = float(di[k][0]);
+          dst[1] = float(di[k][1]);
+        }
+      }
+    } else
     for (int us = w; us < ni_end; us += SYM_WAVES) {
       // this wave's i-subblock us: points s S + 64 us + 8a + r
       float xi[8], yi[8];
