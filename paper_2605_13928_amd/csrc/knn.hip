@@ -420,16 +420,17 @@ __global__ __launch_bounds__(256) void loc_scatter_kernel(const uint16_t* __rest
 // candidate row:  [-2 x~ (d), 1, 1, 1, nh, nm, nl, 0 ...]
 // so that <query_i, candidate_j> = |x~_i|^2 + |x~_j|^2 - 2 <x~_i, x~_j>, the
 // squared distance of the rounded points; |x~|^2 (FP32) is carried as the
-// sum nh + nm + nl of three bf16 parts.  Candidate row n is a point at
-// infinite distance from every query ([0 ..., inf at d + 3, 0 ...]): the
-// tiles past the last point are filled with it, so they need no bounds test.
-__global__ __launch_bounds__(256) void bf16_prep_kernel(const float* __restrict__ X, int64_t n, int d,
+// sum nh + nm + nl of three bf16 parts.  Candidate rows n .. nrows - 1
+// (nrows = n + 1 rounded up to a whole tile) are points at infinite
+// distance from every query ([0 ..., inf at d + 3, 0 ...]): the last tile
+// is filled with them, so the tile loads need no bounds test.
+__global__ __launch_bounds__(256) void bf16_prep_kernel(const float* __restrict__ X, int64_t n, int64_t nrows, int d,
                                                         const int32_t* __restrict__ perm, uint16_t* __restrict__ Xq,
                                                         uint16_t* __restrict__ Xc) {
   const int lane = lane_id();
   const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (row > n) return;
-  if (row == n) {
+  if (row >= nrows) return;
+  if (row >= n) {
     Xc[row * 64 + lane] = lane == d + 3 ? BF16_INF : uint16_t(0);
     return;
   }
@@ -465,6 +466,10 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 constexpr int B_TJ = 64;  // candidates per LDS tile
 
+// candidate rows: the n points and at least one infinite row, up to a
+// whole number of tiles
+__host__ __device__ constexpr int64_t bf16_rows(int64_t n) { return (n + B_TJ) / B_TJ * B_TJ; }
+
 // LDS tile of B_TJ candidate rows, 8 chunks of 16 bytes each; chunk c of
 // row r is stored at r * 8 + (c ^ (r & 7)) so that 16 lanes reading chunk c
 // of 16 consecutive rows hit distinct banks.
@@ -491,51 +496,67 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
   __shared__ uint32_t hist_s[4][256];   // per-wave radix-select histograms
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q16 = lane & 15, g4 = lane >> 4;
-  const int64_t qblock = int64_t(blockIdx.x) * 256;
-  const int64_t qbase = qblock + w * 64;
+  // indices are 32-bit (n < 2^31 is checked by the caller); products that
+  // address memory are taken in 64 bits
+  const int n32 = int(n);
+  const int qblock = int(blockIdx.x) * 256;
+  const int qbase = qblock + w * 64;
   int cnt[4] = {0, 0, 0, 0};  // buffer count of query (t, q16), the same in its four lanes
   // query fragments: tile t, k-step s; lane holds query qbase + 16 t + q16,
   // k elements 32 s + 8 g4 ... + 7
   bf16x8_t bq[4][2];
   float tau[4];
+  // the subtile filter compares raw bit patterns as signed integers: for a
+  // non-negative threshold, d <= tau implies bits(d) <= bits(tau) (a
+  // negative d has a negative pattern), so no candidate that passes is
+  // filtered out; a negative threshold (the padding queries, or a row whose
+  // best distances round below 0) lets every subtile through to the exact
+  // per-candidate test
+  int tau_key[4];
+  auto key_of = [](float t) { return t >= 0.0f ? __float_as_int(t) : INT_MAX; };
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int64_t qi = qbase + t * 16 + q16;
+    const int qi = qbase + t * 16 + q16;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       uint4 v = make_uint4(0, 0, 0, 0);
-      if (qi < n) v = Xq[qi * 8 + s * 4 + g4];
+      if (qi < n32) v = Xq[int64_t(qi) * 8 + s * 4 + g4];
       bq[t][s] = __builtin_bit_cast(bf16x8_t, v);
     }
     // queries past n never accept; the others accept any finite distance
     // until their buffer is first compacted (the padding rows are infinite)
-    tau[t] = qi < n ? FLT_MAX : -INFINITY;
+    tau[t] = qi < n32 ? FLT_MAX : -INFINITY;
+    tau_key[t] = key_of(tau[t]);
   }
   // Tiles go from global memory straight to LDS (global_load_lds_dwordx4:
   // lane l of a wave writes the 16 bytes at the wave's LDS base + 16 l), so
   // the swizzle is applied on the global side: LDS slot u holds chunk
-  // (u % 8) ^ (row % 8) of row u / 8.  Rows past n read the infinite row n.
-  auto load_tile = [&](int64_t c0, uint4* dst) {
+  // (u % 8) ^ (row % 8) of row u / 8.  Rows past n are the infinite rows.
+  // Thread tid loads slots u = tid and tid + 256: a per-thread source
+  // offset fixed for the whole sweep, and a wave-uniform LDS base.
+  uint32_t soff[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int u = tid + 256 * h;
-      const int r = u >> 3;
-      const int64_t g = c0 + r;
-      const uint4* src = Xc + (g < n ? g : n) * 8 + ((u & 7) ^ (r & 7));
-      __builtin_amdgcn_global_load_lds(src, dst + (u & ~63), 16, 0, 0);
-    }
+  for (int h = 0; h < 2; ++h) {
+    const int u = tid + 256 * h;
+    const int r = u >> 3;
+    soff[h] = uint32_t(r * 8 + ((u & 7) ^ (r & 7)));
+  }
+  auto load_tile = [&](int c0, uint4* dst) {
+    const uint4* base = Xc + int64_t(c0) * 8;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) __builtin_amdgcn_global_load_lds(base + soff[h], dst + 64 * w + 256 * h, 16, 0, 0);
   };
-  const int64_t ntiles = (n + B_TJ - 1) / B_TJ;
-  int64_t t0 = (qblock / B_TJ - 2) % ntiles;
+  const int ntiles = (n32 + B_TJ - 1) / B_TJ;
+  int t0 = (qblock / B_TJ - 2) % ntiles;
   if (t0 < 0) t0 += ntiles;
-  auto tile_c0 = [&](int64_t it) -> int64_t {
-    const int64_t ti = t0 + it;
+  auto tile_c0 = [&](int it) -> int {
+    const int ti = t0 + it;
     return (ti < ntiles ? ti : ti - ntiles) * B_TJ;
   };
   load_tile(tile_c0(0), tile[0]);
   int buf = 0;
-  for (int64_t it = 0; it < ntiles; ++it) {
-    const int64_t c0 = tile_c0(it);
+  for (int it = 0; it < ntiles; ++it) {
+    const int c0 = tile_c0(it);
     __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the tile has landed
     __syncthreads();                // ... and every wave's; the other buffer is free
     // fetch the next tile while this one is consumed
@@ -561,12 +582,13 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
         bool any = false;
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-          any |= fminf(fminf(acc[t][0], acc[t][1]), fminf(acc[t][2], acc[t][3])) <= tau[t];
+          any |= min(min(__float_as_int(acc[t][0]), __float_as_int(acc[t][1])),
+                     min(__float_as_int(acc[t][2]), __float_as_int(acc[t][3]))) <= tau_key[t];
         if (__ballot(any)) {
-          const int64_t jb = c0 + sub * 16 + 4 * g4;
+          const int jb = c0 + sub * 16 + 4 * g4;
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const int64_t qi = qbase + t * 16 + q16;
+            const int qi = qbase + t * 16 + q16;
             bool p[4];
             int c = 0;
 #pragma unroll
@@ -586,13 +608,13 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
             cnt[t] += s01 + s23;
             // the buffers of queries qbase + 16 t ..: a wave-uniform base and
             // a small per-lane offset (no 64-bit pointer per query and t)
-            uint64_t* tbuf = bufs + (qbase + t * 16) * CAP;
+            uint64_t* tbuf = bufs + int64_t(qbase + t * 16) * CAP;
             const int lo_off = q16 * CAP;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
               // (a candidate past the last point is at +inf and never passes;
               // the clamp only keeps the index read in bounds regardless)
-              if (p[r]) tbuf[lo_off + pos++] = make_key(fmaxf(acc[t][r], 0.0f), perm[jb + r < n ? jb + r : n - 1]);
+              if (p[r]) tbuf[lo_off + pos++] = make_key(fmaxf(acc[t][r], 0.0f), perm[jb + r < n32 ? jb + r : n32 - 1]);
           }
         }
       }
@@ -610,22 +632,23 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
       const int t = r >> 4, q = r & 15;
       const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], q);
       float nt;
-      const int nc = compact_row<EPL>(bufs + (qbase + r) * CAP, c, ncand, CAP - B_TJ, nt, hist_s[w]);
+      const int nc = compact_row<EPL>(bufs + int64_t(qbase + r) * CAP, c, ncand, CAP - B_TJ, nt, hist_s[w]);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt)
         if (tt == t && q16 == q) {
           cnt[tt] = nc;
           tau[tt] = nt;
+          tau_key[tt] = key_of(nt);
         }
     }
     buf ^= 1;
   }
   for (int r = 0; r < 64; ++r) {
-    const int64_t qi = qbase + r;
-    if (qi >= n) break;
+    const int qi = qbase + r;
+    if (qi >= n32) break;
     const int t = r >> 4;
     const int c = __builtin_amdgcn_readlane(t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3], r & 15);
-    emit_row<EPL>(bufs + qi * CAP, c, ncand, cand + int64_t(perm[qi]) * ncand, nullptr);
+    emit_row<EPL>(bufs + int64_t(qi) * CAP, c, ncand, cand + int64_t(perm[qi]) * ncand, nullptr);
   }
 }
 
@@ -705,7 +728,7 @@ struct KnnLayout {
       L.epl = 8;  // capacity 512, headroom 64 per tile
       L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * 512);
       L.o_xq = c.take(sizeof(uint16_t) * size_t(n) * 64);
-      L.o_xc = c.take(sizeof(uint16_t) * size_t(n + 1) * 64);  // + the infinite row
+      L.o_xc = c.take(sizeof(uint16_t) * size_t(bf16_rows(n)) * 64);  // + the infinite rows
       L.o_cand = c.take(sizeof(int32_t) * size_t(n) * size_t(ncand));
       L.o_perm = c.take(sizeof(int32_t) * size_t(n));
       L.o_key = c.take(sizeof(uint16_t) * size_t(n));
@@ -781,7 +804,8 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   if ((rc = exclusive_scan<int>(hist, LOC_BINS, off, bsum, s))) return rc;
   hipLaunchKernelGGL(loc_scatter_kernel, lgrid, dim3(256), 0, s, key, n, off, cur, perm);
   TSNE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(n + 1, 4))), dim3(256), 0, s, X, n, d, perm, Xq, Xc);
+  hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(bf16_rows(n), 4))), dim3(256), 0, s, X, n, bf16_rows(n),
+                     d, perm, Xq, Xc);
   TSNE_CHECK_LAUNCH();
   hipLaunchKernelGGL(knn_bf16_kernel<8>, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
                      reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), perm, n, n_cand, bufs,
