@@ -493,6 +493,7 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
                                                        uint64_t* __restrict__ bufs, int32_t* __restrict__ cand) {
   constexpr int CAP = 64 * EPL;
   __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
+  __shared__ int32_t ptile[2][B_TJ];    // the original indices of those rows
   __shared__ uint32_t hist_s[4][256];   // per-wave radix-select histograms
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q16 = lane & 15, g4 = lane >> 4;
@@ -541,10 +542,15 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
     const int r = u >> 3;
     soff[h] = uint32_t(r * 8 + ((u & 7) ^ (r & 7)));
   }
-  auto load_tile = [&](int c0, uint4* dst) {
+  // Wave 0 also brings the tile's 64 entries of perm (padded to whole
+  // tiles), so an append reads its candidate's index from LDS.
+  auto load_tile = [&](int c0, int b) {
     const uint4* base = Xc + int64_t(c0) * 8;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) __builtin_amdgcn_global_load_lds(base + soff[h], dst + 64 * w + 256 * h, 16, 0, 0);
+    for (int h = 0; h < 2; ++h) __builtin_amdgcn_global_load_lds(base + soff[h], tile[b] + 64 * w + 256 * h, 16, 0, 0);
+    // (the LDS operand as an explicit element pointer: an array operand is
+    // taken by value by this builtin)
+    if (w == 0) __builtin_amdgcn_global_load_lds(perm + c0 + lane, &ptile[b][0], 4, 0, 0);
   };
   const int ntiles = (n32 + B_TJ - 1) / B_TJ;
   int t0 = (qblock / B_TJ - 2) % ntiles;
@@ -553,15 +559,16 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
     const int ti = t0 + it;
     return (ti < ntiles ? ti : ti - ntiles) * B_TJ;
   };
-  load_tile(tile_c0(0), tile[0]);
+  load_tile(tile_c0(0), 0);
   int buf = 0;
   for (int it = 0; it < ntiles; ++it) {
     const int c0 = tile_c0(it);
     __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the tile has landed
     __syncthreads();                // ... and every wave's; the other buffer is free
     // fetch the next tile while this one is consumed
-    if (it + 1 < ntiles) load_tile(tile_c0(it + 1), tile[buf ^ 1]);
+    if (it + 1 < ntiles) load_tile(tile_c0(it + 1), buf ^ 1);
     const uint4* tl = tile[buf];
+    const int32_t* pt = ptile[buf];
     // tiles that hold some of this block's queries exclude the self pairs;
     // the others need only the threshold test
     auto sweep = [&](auto edge_c) {
@@ -586,6 +593,8 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
                      min(__float_as_int(acc[t][2]), __float_as_int(acc[t][3]))) <= tau_key[t];
         if (__ballot(any)) {
           const int jb = c0 + sub * 16 + 4 * g4;
+          const int4 pj = *reinterpret_cast<const int4*>(pt + sub * 16 + 4 * g4);  // perm[jb .. jb + 3]
+          const int pjr[4] = {pj.x, pj.y, pj.z, pj.w};
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int qi = qbase + t * 16 + q16;
@@ -609,12 +618,10 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
             // the buffers of queries qbase + 16 t ..: a wave-uniform base and
             // a small per-lane offset (no 64-bit pointer per query and t)
             uint64_t* tbuf = bufs + int64_t(qbase + t * 16) * CAP;
-            const int lo_off = q16 * CAP;
+            const uint32_t lo_off = uint32_t(q16 * CAP);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              // (a candidate past the last point is at +inf and never passes;
-              // the clamp only keeps the index read in bounds regardless)
-              if (p[r]) tbuf[lo_off + pos++] = make_key(fmaxf(acc[t][r], 0.0f), perm[jb + r < n32 ? jb + r : n32 - 1]);
+              if (p[r]) tbuf[lo_off + uint32_t(pos++)] = make_key(fmaxf(acc[t][r], 0.0f), pjr[r]);
           }
         }
       }
@@ -730,7 +737,7 @@ struct KnnLayout {
       L.o_xq = c.take(sizeof(uint16_t) * size_t(n) * 64);
       L.o_xc = c.take(sizeof(uint16_t) * size_t(bf16_rows(n)) * 64);  // + the infinite rows
       L.o_cand = c.take(sizeof(int32_t) * size_t(n) * size_t(ncand));
-      L.o_perm = c.take(sizeof(int32_t) * size_t(n));
+      L.o_perm = c.take(sizeof(int32_t) * size_t(bf16_rows(n)));  // padded like the candidate rows
       L.o_key = c.take(sizeof(uint16_t) * size_t(n));
       L.o_rng = c.take(sizeof(uint32_t) * 2 * LOC_DIMS);
       L.o_hist = c.take(sizeof(int) * LOC_BINS);
@@ -804,6 +811,9 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   if ((rc = exclusive_scan<int>(hist, LOC_BINS, off, bsum, s))) return rc;
   hipLaunchKernelGGL(loc_scatter_kernel, lgrid, dim3(256), 0, s, key, n, off, cur, perm);
   TSNE_CHECK_LAUNCH();
+  // the padding of perm (the infinite candidate rows) names point 0; such a
+  // candidate never passes a threshold, so the value is never used
+  if ((rc = launch_fill<int32_t>(perm + n, bf16_rows(n) - n, 0, s))) return rc;
   hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(bf16_rows(n), 4))), dim3(256), 0, s, X, n, bf16_rows(n),
                      d, perm, Xq, Xc);
   TSNE_CHECK_LAUNCH();
