@@ -483,10 +483,10 @@ __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r 
 // t = 0..3, of its wave and, per 16-candidate subtile, on candidates
 // 4 (l / 16) .. + 3 (the MFMA C layout).  A query's threshold and buffer
 // count are held (identically) by its four lanes.  Four blocks fit a CU
-// (at most 128 VGPRs; the selection is bound by memory instructions, so
-// resident waves count more than the few registers the compiler then
-// spills outside the append path), and 1024 resident blocks cover 262144
-// queries in one round.
+// (at most 128 VGPRs, which the kernel fits without VGPR spills; the
+// selection is bound by memory instructions, so resident waves count more
+// than registers), and 1024 resident blocks cover 262144 queries in one
+// round.
 template <int EPL>
 __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
                                                        const int32_t* __restrict__ perm, int64_t n, int ncand,
