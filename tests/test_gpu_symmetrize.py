@@ -46,9 +46,9 @@ def test_symmetrize_random_graphs(dev, n, k, seed):
 
 @pytest.mark.parametrize("n,k,hubs", [(3000, 20, {5: 300, 7: 900, 11: 2999}), (9000, 3, {0: 8999, 1: 5000})])
 def test_symmetrize_hub_rows(dev, n, k, hubs):
-    # hubs with in-lists of ~300, ~900, ~3000, ~5000 and ~9000 entries exercise
-    # every per-row sort path (wave: <= 256, <= 1024; workgroup: LDS bitonic
-    # <= 8192, rank sort beyond)
+    # hubs with in-lists of ~300, ~900, ~3000, ~5000 and ~9000 entries: long
+    # runs of one target in the radix sort of the transposed lists, spanning
+    # many of its 2048-item blocks
     say("symmetrize hubs", n, k)
     rng = np.random.default_rng(9)
     idx = np.empty((n, k), np.int32)
