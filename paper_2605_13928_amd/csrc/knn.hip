@@ -665,8 +665,10 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
 // locality order (wave w re-ranks row perm[w]), so the waves resident at one
 // time gather overlapping candidate rows from the caches.  The query row is
 // read with uniform (scalar) loads; each lane issues all loads of a
-// candidate row before the arithmetic (d <= DMAX).
-template <int DMAX>
+// candidate row before the arithmetic (d <= DMAX), two coordinates per load
+// when the rows are 8-byte aligned (PAIRS: d even and X 8-byte aligned),
+// which halves the scattered requests the address units must serve.
+template <int DMAX, bool PAIRS>
 __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X, int64_t n, int d,
                                                      const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
                                                      int ncand, int k, int32_t* __restrict__ out_idx,
@@ -687,15 +689,26 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X
     if (j >= 0 && j < n) {  // a row short of candidates (non-finite input) holds -1
       const float* xj = X + int64_t(j) * d;
       float xv[DMAX];
+      // no branches on d: coordinates past d re-read the row's last ones
+      // (in bounds) and add an exact 0 to the sum
+      if (PAIRS) {
+        const float2* xj2 = reinterpret_cast<const float2*>(xj);
+        const int last = d / 2 - 1;
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) xv[c] = c < d ? xj[c] : 0.0f;
+        for (int c = 0; c < DMAX; c += 2) {
+          const float2 q = xj2[c / 2 < last ? c / 2 : last];
+          xv[c] = q.x;
+          if (c + 1 < DMAX) xv[c + 1] = q.y;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) xv[c] = xj[c < d ? c : d - 1];
+      }
       float s2 = 0.0f;
 #pragma unroll
       for (int c = 0; c < DMAX; ++c) {
-        if (c < d) {
-          const float u = xi[c] - xv[c];
-          s2 = __builtin_fmaf(u, u, s2);
-        }
+        const float u = c < d ? xi[c] - xv[c] : 0.0f;
+        s2 = __builtin_fmaf(u, u, s2);
       }
       v[t] = make_key(s2, j);
     }
@@ -821,8 +834,12 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
                      reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), perm, n, n_cand, bufs,
                      cand);
   TSNE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(rerank_kernel<TSNE_MAX_D_BF16>, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, perm,
-                     cand, n_cand, k, nbr_idx, nbr_d2);
+  if (d % 2 == 0 && reinterpret_cast<uintptr_t>(X) % 8 == 0)
+    hipLaunchKernelGGL((rerank_kernel<TSNE_MAX_D_BF16, true>), dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n,
+                       d, perm, cand, n_cand, k, nbr_idx, nbr_d2);
+  else
+    hipLaunchKernelGGL((rerank_kernel<TSNE_MAX_D_BF16, false>), dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n,
+                       d, perm, cand, n_cand, k, nbr_idx, nbr_d2);
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
 }
