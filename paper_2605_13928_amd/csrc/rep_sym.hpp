@@ -655,6 +655,99 @@ __global__ __launch_bounds__(256, 2) void rep_sym_kernel(const float2* __restric
   if (tid == 0) Zblock[blockIdx.x] = bz;
 }
 
+// Z alone (the KL's forward): the sum of w over all ordered pairs i != j
+// with the decomposition, job dealing and diagonal tiles of rep_sym_kernel
+// but no per-point sums, so a pair costs the two differences, the two FMAs
+// of q, the reciprocal and one add.  Per workgroup one FP64 partial (each
+// tile's FP32 sum folded into FP64), in Zblock[blockIdx.x].
+template <bool DIAG>
+__device__ __forceinline__ void sym_tile_z(const float (&xi)[8], const float (&yi)[8], const float4 (&pjv)[4],
+                                           float& z, bool same_group) {
+  float xj[8], yj[8];
+#pragma unroll
+  for (int c = 0; c < 8; c += 2) {
+    const float4 v = pjv[c / 2];
+    xj[c] = v.x;
+    yj[c] = v.y;
+    xj[c + 1] = v.z;
+    yj[c + 1] = v.w;
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float dx = xi[r] - xj[c], dy = yi[r] - yj[c];
+      float w = __builtin_amdgcn_rcpf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f)));
+      if (DIAG && r == c) w = same_group ? 0.0f : w;
+      z += w;
+    }
+  }
+}
+
+template <int PF>
+__global__ __launch_bounds__(256) void zsum_sym_kernel(const float2* __restrict__ Y, int64_t n, int64_t ns,
+                                                       double* __restrict__ Zblock) {
+  constexpr int S = 256 * PF;
+  __shared__ __attribute__((aligned(16))) float2 ipts[S];
+  __shared__ __attribute__((aligned(16))) float2 jpts[S];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int a = lane >> 3, b = lane & 7;
+  const int nsub = S / 64;
+  const int64_t njobs = ns * (ns + 1) / 2;
+  const int64_t P = gridDim.x;
+  const int64_t nj_last = min(int64_t(nsub), (n - (ns - 1) * S + 63) / 64);
+  const bool last_first = 2 * nj_last > nsub + 1;
+  double zsum = 0.0;
+  for (int64_t rnd = 0;; ++rnd) {
+    const int64_t pos = rnd * P + ((rnd & 1) ? P - 1 - int64_t(blockIdx.x) : int64_t(blockIdx.x));
+    if (pos >= njobs) break;
+    int64_t s, t;
+    job_pair(sym_sched(pos, ns, last_first), ns, s, t);
+    const bool diag_sb = s == t;
+    __syncthreads();  // the previous job's points are no longer read
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int u = tid + 256 * k;
+      ipts[u] = load_point(Y, s * S + u, n);
+      jpts[u] = load_point(Y, t * S + u, n);
+    }
+    __syncthreads();
+    const int ni_end = int(min(int64_t(nsub), (n - s * S + 63) / 64));
+    const int nj_end = int(min(int64_t(nsub), (n - t * S + 63) / 64));
+    for (int us = w; us < ni_end; us += SYM_WAVES) {
+      float xi[8], yi[8];
+#pragma unroll
+      for (int r = 0; r < 8; r += 2) {
+        const float4 v = *reinterpret_cast<const float4*>(ipts + 64 * us + 8 * a + r);
+        xi[r] = v.x;
+        yi[r] = v.y;
+        xi[r + 1] = v.z;
+        yi[r + 1] = v.w;
+      }
+      const int ntile = diag_sb ? (us < nsub / 2 ? nsub / 2 + 1 : nsub / 2) : nj_end;
+      for (int e = 0; e < ntile; ++e) {
+        const int v = diag_sb ? (us + e < nsub ? us + e : us + e - nsub) : e;
+        if (v >= nj_end) continue;
+        float4 jc[4];
+        const float4* p = reinterpret_cast<const float4*>(jpts + 64 * v + 8 * b);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) jc[c] = p[c];
+        float z = 0.0f;
+        if (diag_sb && v == us) {
+          sym_tile_z<true>(xi, yi, jc, z, a == b);
+          zsum += double(z);
+        } else {
+          sym_tile_z<false>(xi, yi, jc, z, false);
+          zsum += 2.0 * double(z);
+        }
+      }
+    }
+  }
+  const double bz = block_sum_d(zsum, red);
+  if (tid == 0) Zblock[blockIdx.x] = bz;
+}
+
 inline size_t rep_sym_lds_bytes(int64_t S, bool zrow, bool att) {
   const int nc = zrow ? 3 : 2;
   const bool sep = att && S < 1024;  // ATT_SEP of the kernel
