@@ -127,13 +127,112 @@ __global__ __launch_bounds__(256) void umap_wmax_final_kernel(float* __restrict_
   if (threadIdx.x == 0) *wmax = red[0];
 }
 
+// Memory-level parallelism of the epoch kernels: a thread's loads are
+// issued in batches (the values and columns of UMAP_EB entries, the y_j of
+// the sampled ones, the y_c of up to UMAP_NB negatives) before any of them
+// is used, instead of one dependent round trip per load.  The steps are
+// summed in 64-bit fixed point, so the order in which a batch is consumed
+// does not change a bit of the result.
+constexpr int UMAP_EB = 8;  // entries per batch
+constexpr int UMAP_NB = 8;  // negatives per batch
+
+// The neg_rate repulsive steps of sampled entry e of row i (counter base
+// (t nnz + e) neg_rate), added to (ax, ay).
+__device__ __forceinline__ void umap_negatives(const float2* __restrict__ Y, int64_t n, int64_t i, float2 yi,
+                                               uint64_t seed, uint64_t base, int neg_rate, float a, float b,
+                                               float alpha, long long& ax, long long& ay) {
+  const float c2b = 2.0f * b;
+  for (int p0 = 0; p0 < neg_rate; p0 += UMAP_NB) {
+    int64_t c[UMAP_NB];
+    float2 yc[UMAP_NB];
+#pragma unroll
+    for (int u = 0; u < UMAP_NB; ++u) {
+      const int p = p0 + u;
+      const uint64_t z = splitmix64(seed, base + uint64_t(p));
+      // slots past neg_rate stand on i itself and are skipped like a draw of i
+      c[u] = p < neg_rate ? int64_t(((z >> 32) * uint64_t(n)) >> 32) : i;
+    }
+#pragma unroll
+    for (int u = 0; u < UMAP_NB; ++u) yc[u] = Y[c[u]];
+#pragma unroll
+    for (int u = 0; u < UMAP_NB; ++u) {
+      if (c[u] == i) continue;
+      const float ex = yi.x - yc[u].x, ey = yi.y - yc[u].y;
+      const float q2 = ex * ex + ey * ey;
+      if (q2 > 0.0f) {
+        const float cr = c2b / ((UMAP_EPS + q2) * (1.0f + a * powf(q2, b)));
+        ax += umap_fx(alpha * umap_clip(cr * ex));
+        ay += umap_fx(alpha * umap_clip(cr * ey));
+      }
+    }
+  }
+}
+
 // Epoch t, one thread per row i of the CSR graph: for every entry (i, j)
 // sampled in this epoch, the attractive step alpha clip(c_a (y_i - y_j))
-// added to y_i and subtracted from y_j, then neg_rate repulsive steps
-// alpha clip(c_r (y_i - y_c)) added to y_i; c_a = -2ab d2^(b-1) / (1 + a
-// d2^b), c_r = 2b / ((eps + d2)(1 + a d2^b)), no step at d2 = 0 or for a
-// draw c = i.  Steps into y_i are summed in registers (fixed point) and
-// added once; steps into y_j go straight to D with 64-bit integer atomics.
+// added to y_i and, with SCATTER, subtracted from y_j (64-bit integer
+// atomics into D), else added to y_i a second time (a symmetric graph, see
+// umap_epoch_sym_kernel); then neg_rate repulsive steps alpha clip(c_r (y_i
+// - y_c)) added to y_i; c_a = -2ab d2^(b-1) / (1 + a d2^b), c_r = 2b / ((eps
+// + d2)(1 + a d2^b)), no step at d2 = 0 or for a draw c = i.  Steps into y_i
+// are summed in registers (fixed point): returned in (ax, ay).
+template <bool SCATTER>
+__device__ __forceinline__ void umap_row_epoch(const float2* __restrict__ Y, int64_t n, int64_t i, float2 yi,
+                                               const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                               const float* __restrict__ val, int64_t nnz, float rmax, float a,
+                                               float b, float alpha, int neg_rate, uint64_t seed, int t,
+                                               unsigned long long* __restrict__ D, long long& ax, long long& ay) {
+  const float t0 = float(t), t1 = float(t + 1);
+  const float cab = -2.0f * a * b;
+  const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+  for (int64_t eb = e0; eb < e1; eb += UMAP_EB) {
+    float v[UMAP_EB];
+    int32_t cj[UMAP_EB];
+#pragma unroll
+    for (int u = 0; u < UMAP_EB; ++u) {
+      const int64_t e = eb + u;
+      v[u] = e < e1 ? val[e] : 0.0f;  // (0: never sampled)
+      cj[u] = e < e1 ? col[e] : int32_t(i);
+    }
+    bool smp[UMAP_EB];
+    float2 yj[UMAP_EB];
+#pragma unroll
+    for (int u = 0; u < UMAP_EB; ++u) {
+      const float r = __fdiv_rn(v[u], rmax);  // correctly rounded, as the schedule requires
+      smp[u] = eb + u < e1 && floorf(t1 * r) > floorf(t0 * r);
+      yj[u] = Y[smp[u] ? int64_t(cj[u]) : i];
+    }
+    // all eight gathers in flight before the first is used (else the
+    // compiler sinks each into its sampled branch, one round trip each)
+#pragma unroll
+    for (int u = 0; u < UMAP_EB; ++u) asm volatile("" : "+v"(yj[u].x), "+v"(yj[u].y));
+#pragma unroll
+    for (int u = 0; u < UMAP_EB; ++u) {
+      if (!smp[u]) continue;
+      const float dx = yi.x - yj[u].x, dy = yi.y - yj[u].y;
+      const float d2 = dx * dx + dy * dy;
+      if (d2 > 0.0f) {
+        const float pb = powf(d2, b);
+        const float c = cab * (pb / d2) / (1.0f + a * pb);
+        const long long fx = umap_fx(alpha * umap_clip(c * dx)), fy = umap_fx(alpha * umap_clip(c * dy));
+        if (SCATTER) {
+          ax += fx;
+          ay += fy;
+          atomicAdd(&D[2 * int64_t(cj[u])], static_cast<unsigned long long>(-fx));
+          atomicAdd(&D[2 * int64_t(cj[u]) + 1], static_cast<unsigned long long>(-fy));
+        } else {
+          ax += 2 * fx;
+          ay += 2 * fy;
+        }
+      }
+      const uint64_t base = (uint64_t(t) * uint64_t(nnz) + uint64_t(eb + u)) * uint64_t(neg_rate);
+      umap_negatives(Y, n, i, yi, seed, base, neg_rate, a, b, alpha, ax, ay);
+    }
+  }
+}
+
+// Epoch t on any graph: steps into y_j go straight to D with 64-bit
+// integer atomics, y_i's own sum is added once.
 __global__ __launch_bounds__(256) void umap_epoch_kernel(const float2* __restrict__ Y, int64_t n,
                                                          const int64_t* __restrict__ row_ptr,
                                                          const int32_t* __restrict__ col,
@@ -143,43 +242,8 @@ __global__ __launch_bounds__(256) void umap_epoch_kernel(const float2* __restric
                                                          unsigned long long* __restrict__ D) {
   const int64_t i = gtid();
   if (i >= n) return;
-  const float rmax = *wmax;
-  const float t0 = float(t), t1 = float(t + 1);
-  const float2 yi = Y[i];
-  const float cab = -2.0f * a * b, c2b = 2.0f * b;
   long long ax = 0, ay = 0;
-  const int64_t e1 = row_ptr[i + 1];
-  for (int64_t e = row_ptr[i]; e < e1; ++e) {
-    const float r = __fdiv_rn(val[e], rmax);  // correctly rounded, as the schedule requires
-    if (!(floorf(t1 * r) > floorf(t0 * r))) continue;
-    const int32_t j = col[e];
-    const float2 yj = Y[j];
-    const float dx = yi.x - yj.x, dy = yi.y - yj.y;
-    const float d2 = dx * dx + dy * dy;
-    if (d2 > 0.0f) {
-      const float pb = powf(d2, b);
-      const float c = cab * (pb / d2) / (1.0f + a * pb);
-      const long long fx = umap_fx(alpha * umap_clip(c * dx)), fy = umap_fx(alpha * umap_clip(c * dy));
-      ax += fx;
-      ay += fy;
-      atomicAdd(&D[2 * int64_t(j)], static_cast<unsigned long long>(-fx));
-      atomicAdd(&D[2 * int64_t(j) + 1], static_cast<unsigned long long>(-fy));
-    }
-    const uint64_t base = (uint64_t(t) * uint64_t(nnz) + uint64_t(e)) * uint64_t(neg_rate);
-    for (int p = 0; p < neg_rate; ++p) {
-      const uint64_t z = splitmix64(seed, base + uint64_t(p));
-      const int64_t c = int64_t(((z >> 32) * uint64_t(n)) >> 32);
-      if (c == i) continue;
-      const float2 yc = Y[c];
-      const float ex = yi.x - yc.x, ey = yi.y - yc.y;
-      const float q2 = ex * ex + ey * ey;
-      if (q2 > 0.0f) {
-        const float cr = c2b / ((UMAP_EPS + q2) * (1.0f + a * powf(q2, b)));
-        ax += umap_fx(alpha * umap_clip(cr * ex));
-        ay += umap_fx(alpha * umap_clip(cr * ey));
-      }
-    }
-  }
+  umap_row_epoch<true>(Y, n, i, Y[i], row_ptr, col, val, nnz, *wmax, a, b, alpha, neg_rate, seed, t, D, ax, ay);
   if (ax) atomicAdd(&D[2 * i], static_cast<unsigned long long>(ax));
   if (ay) atomicAdd(&D[2 * i + 1], static_cast<unsigned long long>(ay));
 }
@@ -215,39 +279,10 @@ __global__ __launch_bounds__(256) void umap_epoch_sym_kernel(const float2* __res
                                                              float alpha, int neg_rate, uint64_t seed, int t) {
   const int64_t i = gtid();
   if (i >= n) return;
-  const float rmax = *wmax;
-  const float t0 = float(t), t1 = float(t + 1);
   const float2 yi = Yin[i];
-  const float cab = -2.0f * a * b, c2b = 2.0f * b;
   long long ax = 0, ay = 0;
-  const int64_t e1 = row_ptr[i + 1];
-  for (int64_t e = row_ptr[i]; e < e1; ++e) {
-    const float r = __fdiv_rn(val[e], rmax);
-    if (!(floorf(t1 * r) > floorf(t0 * r))) continue;
-    const float2 yj = Yin[col[e]];
-    const float dx = yi.x - yj.x, dy = yi.y - yj.y;
-    const float d2 = dx * dx + dy * dy;
-    if (d2 > 0.0f) {
-      const float pb = powf(d2, b);
-      const float c = cab * (pb / d2) / (1.0f + a * pb);
-      ax += 2 * umap_fx(alpha * umap_clip(c * dx));
-      ay += 2 * umap_fx(alpha * umap_clip(c * dy));
-    }
-    const uint64_t base = (uint64_t(t) * uint64_t(nnz) + uint64_t(e)) * uint64_t(neg_rate);
-    for (int p = 0; p < neg_rate; ++p) {
-      const uint64_t z = splitmix64(seed, base + uint64_t(p));
-      const int64_t c = int64_t(((z >> 32) * uint64_t(n)) >> 32);
-      if (c == i) continue;
-      const float2 yc = Yin[c];
-      const float ex = yi.x - yc.x, ey = yi.y - yc.y;
-      const float q2 = ex * ex + ey * ey;
-      if (q2 > 0.0f) {
-        const float cr = c2b / ((UMAP_EPS + q2) * (1.0f + a * powf(q2, b)));
-        ax += umap_fx(alpha * umap_clip(cr * ex));
-        ay += umap_fx(alpha * umap_clip(cr * ey));
-      }
-    }
-  }
+  umap_row_epoch<false>(Yin, n, i, yi, row_ptr, col, val, nnz, *wmax, a, b, alpha, neg_rate, seed, t, nullptr, ax,
+                        ay);
   float2 y = yi;
   y.x += float(double(ax) * (1.0 / 4294967296.0));
   y.y += float(double(ay) * (1.0 / 4294967296.0));

@@ -82,3 +82,18 @@ def test_fp64_forward_backward_tight(dev):
     assert abs(C - Co) <= 1e-10 * max(1.0, abs(Co))
     assert rel(dY, dYo) <= 1e-10
     assert rel(dP, dPo) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [3001, 40_000, 70_001])
+def test_fp32_forward_Z_and_kl_match_the_gradient_pass(dev, n):
+    # The FP32 forward takes Z from the Z-only symmetric pass; the gradient
+    # pass sums the same weights with its own kernel.  Sizes cover the three
+    # superblock widths (256, 512, 1024 points) with ragged last superblocks.
+    say("autograd fp32 Z vs gradient pass", n)
+    idx, d2, Pc, S = random_graph_P(n, 30, 10.0, 7 + n % 13)
+    P = sparse_to_dev(S, dev)
+    Y = to_dev(synth.random_embedding(n, 4.0, 11 + n % 7), dev)
+    C, Zf = api.kl_forward(Y, P.val, P)
+    _, Zg, klg, _ = api.kl_grad(Y, P, 1.0, want_Z=True, want_kl=True)
+    assert abs(Zf.item() - Zg.item()) <= 1e-6 * Zg.item()
+    assert abs(C.item() - klg.item()) <= 1e-5 * max(1.0, abs(klg.item()))
