@@ -16,10 +16,12 @@
 // new threshold.  The true k best always satisfy d <= tau, so nothing is
 // lost; ties at tau are kept and resolved by index in the final sort (a
 // wave-wide bitonic sort of the (d, j) keys).  Since the kept keys are the
-// best ones whatever order the candidates arrive in, the BF16 path sweeps
-// them in a locality order (points sorted by a Morton key of their leading
+// best ones whatever order the candidates arrive in, both paths sweep them
+// in a locality order (points sorted by a Morton key of their leading
 // coordinates, each query block starting next to its own queries), so that
-// tau is tight after a few tiles and few candidates are appended.
+// tau is tight after a few tiles and few candidates are appended, and skip
+// the candidate tiles whose bounding box lies beyond every threshold of
+// the block (a bound that leaves the results those of the full sweep).
 #include <cfloat>
 #include <type_traits>
 
@@ -163,10 +165,22 @@ __device__ void emit_row(const uint64_t* __restrict__ buf, int c, int keep, int3
 }
 
 // ---------------------------------------------------------------------
+// Tile skipping (both paths).  The points are put in a locality order
+// (below), so that a tile of consecutive positions is narrow in the leading
+// coordinates; a tile whose box is farther from the box of a block's
+// queries than every threshold of the block can hold no candidate for it,
+// and the sweep skips it.  Boxes span the leading BOX_D coordinates.
+constexpr int BOX_D = 16;
+
+// ---------------------------------------------------------------------
 // FP32 exact path.  Block = 4 waves x RW rows (RW = 16, or 8 where that
 // gives the busiest CU fewer rows: fknn_small_blocks); each step covers 128
 // columns, 2 per lane; the rows' coordinates are LDS broadcasts, the
-// columns' are per-lane LDS reads, dimension chunks of 56.
+// columns' are per-lane LDS reads, dimension chunks of 56.  Rows and
+// columns are positions of the locality order (Xs = X in that order; perm
+// maps a position to its point, which keys and outputs name); a block
+// sweeps the column tiles cyclically from the one before its own rows and
+// skips those its box test rules out.
 
 constexpr int F_COLS = 128;
 constexpr int F_DC = 56;
@@ -204,8 +218,52 @@ __device__ __forceinline__ void stage_rows_t(float* __restrict__ dst, int stride
   }
 }
 
+// Boxes of the FP32 column tiles: tile u holds positions F_COLS u ..
+// F_COLS u + F_COLS - 1 of Xs (those below n); box[u][c] = (min, max) of
+// coordinate c < BOX_D ((0, 0) past d; NaN left out).  Lane 16 g + c scans
+// coordinate c of rows g, g + 4, ...; the four groups merge by lane
+// exchange.
+__global__ __launch_bounds__(256) void f32_box_kernel(const float* __restrict__ Xs, int64_t n, int d, int64_t ntiles,
+                                                      float2* __restrict__ box) {
+  const int lane = lane_id(), c = lane & 15, g = lane >> 4;
+  const int64_t u = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (u >= ntiles) return;
+  const int64_t r0 = u * F_COLS;
+  const int rows = int(n - r0 < F_COLS ? n - r0 : F_COLS);
+  float lo = INFINITY, hi = -INFINITY;
+  if (c < d) {
+    for (int r = g; r < rows; r += 4) {
+      const float v = Xs[(r0 + r) * d + c];
+      lo = fminf(lo, v);
+      hi = fmaxf(hi, v);
+    }
+  }
+  lo = fminf(lo, xor_lane_f(lo, 16));
+  lo = fminf(lo, xor_lane_f(lo, 32));
+  hi = fmaxf(hi, xor_lane_f(hi, 16));
+  hi = fmaxf(hi, xor_lane_f(hi, 32));
+  if (lane < BOX_D) box[u * BOX_D + lane] = lane < d ? make_float2(lo, hi) : make_float2(0.0f, 0.0f);
+}
+
+// Xs[p] = X[perm[p]]: the rows in the locality order, one wave per row.
+__global__ __launch_bounds__(256) void gather_rows_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                          const int32_t* __restrict__ perm, float* __restrict__ Xs) {
+  const int64_t p = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const int64_t src = perm[p];
+  for (int c = lane_id(); c < d; c += 64) Xs[p * d + c] = X[src * d + c];
+}
+
+// Skipping test of the FP32 path.  Its distance sums d non-negative terms
+// (a rounded difference, squared and added by one FMA each), so it is at
+// least (1 - (d + 2) u) >= 1 - 2^-15 of the exact one for d <= 256; the
+// box bound LB (16 terms) is within 2^-19 of exact.  LB (1 - 2^-12) >
+// tau_max therefore means every distance of the tile exceeds every
+// threshold of the block: it would append nothing, and skipping it leaves
+// the buffers, and the outputs, as the full sweep makes them.
 template <int EPL, int F_RW>
-__global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__ X, int64_t n, int d, int k,
+__global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restrict__ Xs, const int32_t* __restrict__ perm,
+                                                       const float4* __restrict__ cbox4, int64_t n, int d, int k,
                                                        uint64_t* __restrict__ bufs, int32_t* __restrict__ out_idx,
                                                        float* __restrict__ out_d2) {
   static_assert(F_RW == 8 || F_RW == 16, "rows per wave");
@@ -215,25 +273,94 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
   __shared__ __attribute__((aligned(16))) float xi_s[F_DC * XI_S];
   __shared__ __attribute__((aligned(16))) float xj_s[F_DC * XJ_S];
   __shared__ uint32_t hist_s[4][256];  // per-wave radix-select histograms
+  __shared__ int32_t pj_s[F_COLS];     // the points of the staged columns
+  __shared__ float4 qbox[BOX_D / 2];   // box of the block's rows: (lo, hi) of two coordinates each
+  __shared__ float tmax_s[2][4];       // each wave's largest threshold, by tile parity
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t row0 = int64_t(blockIdx.x) * F_ROWS;
   __shared__ int cnt_s[F_ROWS];  // buffer counts (appended by LDS atomics)
-  if (tid < F_ROWS) cnt_s[tid] = 0;  // published by the first staging barrier
+  if (tid < F_ROWS) cnt_s[tid] = 0;  // published by the first barrier
   // per row of this wave (uniform): threshold
   float tau[F_RW];
 #pragma unroll
   for (int r = 0; r < F_RW; ++r) tau[r] = row0 + w * F_RW + r < n ? INFINITY : -INFINITY;  // rows past n never accept
+  if (w == 0) {
+    // the block's box (rows past n left out)
+    const int c = lane & 15, g = lane >> 4;
+    float lo = INFINITY, hi = -INFINITY;
+    if (c < d) {
+      for (int r = g; r < F_ROWS && row0 + r < n; r += 4) {
+        const float v = Xs[(row0 + r) * d + c];
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+      }
+    }
+    lo = fminf(lo, xor_lane_f(lo, 16));
+    lo = fminf(lo, xor_lane_f(lo, 32));
+    hi = fmaxf(hi, xor_lane_f(hi, 16));
+    hi = fmaxf(hi, xor_lane_f(hi, 32));
+    if (lane < BOX_D) reinterpret_cast<float2*>(qbox)[lane] = lane < d ? make_float2(lo, hi) : make_float2(0.0f, 0.0f);
+    if (lane < 4) tmax_s[1][lane] = INFINITY;
+  }
   const bool one_chunk = d <= F_DC;
-  if (one_chunk) stage_rows_t(xi_s, XI_S, X, row0, F_ROWS, n, d, 0, d);
-  for (int64_t c0 = 0; c0 < n; c0 += F_COLS) {
+  if (one_chunk) stage_rows_t(xi_s, XI_S, Xs, row0, F_ROWS, n, d, 0, d);
+  const int ntc = int((n + F_COLS - 1) / F_COLS);
+  int tstart = int(row0 / F_COLS) - 1;
+  if (tstart < 0) tstart += ntc;
+  auto tile_of = [&](int it) -> int {
+    const int ti = tstart + it;
+    return ti < ntc ? ti : ti - ntc;
+  };
+  // live positions of the window [p0, p0 + 64) under the threshold bound tm
+  auto window = [&](int p0, float tm) -> uint64_t {
+    const int p = p0 + lane;
+    bool live = p < ntc;
+    if (tm < INFINITY) {
+      const float4* tb = cbox4 + tile_of(live ? p : 0) * (BOX_D / 2);
+      float lb = 0.0f;
+#pragma unroll 2
+      for (int h = 0; h < BOX_D / 2; ++h) {
+        const float4 v = tb[h], q = qbox[h];  // (lo, hi) of coordinates 2h and 2h + 1
+        const float g0 = fmaxf(fmaxf(v.x - q.y, q.x - v.y), 0.0f);
+        const float g1 = fmaxf(fmaxf(v.z - q.w, q.z - v.w), 0.0f);
+        lb = fmaf(g0, g0, lb);
+        lb = fmaf(g1, g1, lb);
+      }
+      live = live && !(lb * (1.0f - 1.0f / 4096.0f) > tm);
+    }
+    return __ballot(live);
+  };
+  int wb = -64;  // first position of the current window (none yet)
+  uint64_t win = 0;
+  int from = 0, par = 0;
+  for (;;) {
+    __syncthreads();  // every wave is done with the previous tile; thresholds published
+    const float tm = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(
+        fmaxf(fmaxf(tmax_s[par ^ 1][0], tmax_s[par ^ 1][1]), fmaxf(tmax_s[par ^ 1][2], tmax_s[par ^ 1][3])))));
+    int pos = from;
+    while (pos < ntc) {
+      if (pos >= wb + 64) {
+        wb = pos;
+        win = window(wb, tm);
+      }
+      const uint64_t m = win >> (pos - wb);
+      if (m) {
+        pos += __builtin_ctzll(m);
+        break;
+      }
+      pos = wb + 64;
+    }
+    if (pos >= ntc) break;
+    const int64_t c0 = int64_t(tile_of(pos)) * F_COLS;
     float acc[F_RW][2];
 #pragma unroll
     for (int r = 0; r < F_RW; ++r) acc[r][0] = acc[r][1] = 0.0f;
     for (int dc = 0; dc < d; dc += F_DC) {
       const int dl = (d - dc) < F_DC ? (d - dc) : F_DC;
-      __syncthreads();
-      if (!one_chunk) stage_rows_t(xi_s, XI_S, X, row0, F_ROWS, n, d, dc, dl);
-      stage_rows_t(xj_s, XJ_S, X, c0, F_COLS, n, d, dc, dl);
+      if (dc > 0) __syncthreads();
+      if (!one_chunk) stage_rows_t(xi_s, XI_S, Xs, row0, F_ROWS, n, d, dc, dl);
+      stage_rows_t(xj_s, XJ_S, Xs, c0, F_COLS, n, d, dc, dl);
+      if (dc == 0 && tid < F_COLS) pj_s[tid] = c0 + tid < n ? perm[c0 + tid] : -1;
       __syncthreads();
       for (int c = 0; c < dl; ++c) {
         const float4* ap = reinterpret_cast<const float4*>(&xi_s[c * XI_S + w * F_RW]);
@@ -264,6 +391,7 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
     if (__ballot(any)) {
       const bool edge = (c0 + F_COLS > n) || (c0 < row0 + F_ROWS && row0 < c0 + F_COLS);
       const int64_t j0 = c0 + lane * 2;
+      const int32_t pj0 = pj_s[lane * 2], pj1 = pj_s[lane * 2 + 1];
 #pragma unroll
       for (int r = 0; r < F_RW; ++r) {
         const int64_t gi = row0 + w * F_RW + r;
@@ -271,10 +399,10 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
         const bool p1 = acc[r][1] <= tau[r] && (!edge || (j0 + 1 < n && j0 + 1 != gi));
         const int c = int(p0) + int(p1);
         if (c) {
-          int pos = atomicAdd(&cnt_s[w * F_RW + r], c);
+          int slot = atomicAdd(&cnt_s[w * F_RW + r], c);
           uint64_t* buf = bufs + gi * CAP;
-          if (p0) buf[pos++] = make_key(acc[r][0], int32_t(j0));
-          if (p1) buf[pos] = make_key(acc[r][1], int32_t(j0 + 1));
+          if (p0) buf[slot++] = make_key(acc[r][0], pj0);
+          if (p1) buf[slot] = make_key(acc[r][1], pj1);
         }
       }
       // compaction of rows that could overflow in the next step
@@ -292,11 +420,22 @@ __global__ __launch_bounds__(256) void knn_fp32_kernel(const float* __restrict__
           if (rr == r) tau[rr] = nt;
       }
     }
+    // this wave's largest threshold (uniform per row), read by every wave
+    // after the next barrier
+    if (lane == 0) {
+      float m = tau[0];
+#pragma unroll
+      for (int r = 1; r < F_RW; ++r) m = fmaxf(m, tau[r]);
+      tmax_s[par][w] = m;
+    }
+    par ^= 1;
+    from = pos + 1;
   }
   for (int r = 0; r < F_RW; ++r) {
     const int64_t gi = row0 + w * F_RW + r;
     if (gi >= n) break;
-    emit_row<EPL>(bufs + gi * CAP, cnt_s[w * F_RW + r], k, out_idx + gi * k, out_d2 + gi * k);
+    const int64_t pt = perm[gi];
+    emit_row<EPL>(bufs + gi * CAP, cnt_s[w * F_RW + r], k, out_idx + pt * k, out_d2 + pt * k);
   }
 }
 
@@ -314,7 +453,7 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(
 constexpr uint16_t BF16_ONE = 0x3F80;
 constexpr uint16_t BF16_INF = 0x7F80;
 
-// Locality order of the BF16 path.  Points are counting-sorted by a 16-bit
+// Locality order (both paths).  Points are counting-sorted by a 16-bit
 // Morton key of their first three coordinates (6, 5 and 5 bits over each
 // coordinate's range; fewer coordinates when d < 3): position p of the
 // sorted order holds point perm[p].  Within a key the order is that of the
@@ -470,6 +609,32 @@ constexpr int B_TJ = 64;  // candidates per LDS tile
 // whole number of tiles
 __host__ __device__ constexpr int64_t bf16_rows(int64_t n) { return (n + B_TJ) / B_TJ * B_TJ; }
 
+// Tile boxes for skipping candidate tiles.  Tile u holds rows
+// 64 u .. 64 u + 63 of the locality order (those below n); box[u][c] is
+// the (min, max) of the rounded coordinate c over them for c < BOX_D
+// ((0, 0) past d), and tnrm[u] bounds their squared norms from above: the
+// leading bf16 part nh of a row's FP32 norm is within 2^-9 of it
+// (round to nearest), so max nh (1 + 2^-7) bounds the norm.  NaN values
+// are left out of the box and of the bound; such a row's distances are
+// NaN and never pass a threshold.
+__global__ __launch_bounds__(256) void bf16_box_kernel(const uint16_t* __restrict__ Xq, int64_t n, int d,
+                                                       int64_t ntiles, float2* __restrict__ box,
+                                                       float* __restrict__ tnrm) {
+  const int lane = lane_id();
+  const int64_t u = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (u >= ntiles) return;
+  const int64_t r0 = u * B_TJ;
+  const int rows = int(n - r0 < B_TJ ? n - r0 : B_TJ);
+  float lo = INFINITY, hi = -INFINITY;
+  for (int r = 0; r < rows; ++r) {
+    const float v = bf16_to_f(Xq[(r0 + r) * 64 + lane]);
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+  }
+  if (lane < BOX_D) box[u * BOX_D + lane] = lane < d ? make_float2(lo, hi) : make_float2(0.0f, 0.0f);
+  if (lane == d) tnrm[u] = hi * (1.0f + 1.0f / 128.0f);
+}
+
 // LDS tile of B_TJ candidate rows, 8 chunks of 16 bytes each; chunk c of
 // row r is stored at r * 8 + (c ^ (r & 7)) so that 16 lanes reading chunk c
 // of 16 consecutive rows hit distinct banks.
@@ -487,14 +652,34 @@ __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r 
 // selection is bound by memory instructions, so resident waves count more
 // than registers), and 1024 resident blocks cover 262144 queries in one
 // round.
+// Tile skipping.  A tile is neither fetched nor evaluated when no distance
+// in it can pass the threshold of any of the block's queries: with B the
+// box of the block's queries and T the tile's (leading BOX_D coordinates),
+// LB = sum_c gap_c(B, T)^2 is at most the squared distance of any query to
+// any candidate of the tile, and the MFMA's distance differs from the
+// exact one of the rounded points by less than 2^-15 (N_q + N_c) (64
+// products of exact bf16 pairs, FP32 accumulation; N the squared norms, a
+// sum of absolute terms of at most 2 (N_q + N_c); the norm's bf16 parts
+// add 2^-20 of it), so LB > tau_max + 2^-12 (N_q + N_c), with tau_max the
+// block's largest threshold, means every distance of the tile exceeds
+// every query's threshold: the tile would append nothing, and skipping it
+// changes no buffer.  The outputs are those of the full sweep, bit for bit.
+// The test is taken for windows of 64 sweep positions at a time (one
+// position per lane), with the thresholds the waves published at the end
+// of the previous tile; they only decrease, so a stale value skips less,
+// never wrongly.
 template <int EPL>
 __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
-                                                       const int32_t* __restrict__ perm, int64_t n, int ncand,
+                                                       const int32_t* __restrict__ perm, const float4* __restrict__ box4,
+                                                       const float* __restrict__ tnrm, int64_t n, int ncand,
                                                        uint64_t* __restrict__ bufs, int32_t* __restrict__ cand) {
   constexpr int CAP = 64 * EPL;
   __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
   __shared__ int32_t ptile[2][B_TJ];    // the original indices of those rows
   __shared__ uint32_t hist_s[4][256];   // per-wave radix-select histograms
+  __shared__ float4 qbox[BOX_D / 2];    // box of the block's queries: (lo, hi) of two coordinates each
+  __shared__ float qnrm_s;              // bound on the squared norms of the block's queries
+  __shared__ float tmax_s[2][4];        // each wave's largest threshold, by tile parity
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q16 = lane & 15, g4 = lane >> 4;
   // indices are 32-bit (n < 2^31 is checked by the caller); products that
@@ -555,18 +740,79 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
   const int ntiles = (n32 + B_TJ - 1) / B_TJ;
   int t0 = (qblock / B_TJ - 2) % ntiles;
   if (t0 < 0) t0 += ntiles;
-  auto tile_c0 = [&](int it) -> int {
+  auto tile_of = [&](int it) -> int {
     const int ti = t0 + it;
-    return (ti < ntiles ? ti : ti - ntiles) * B_TJ;
+    return ti < ntiles ? ti : ti - ntiles;
   };
+  auto tile_c0 = [&](int it) -> int { return tile_of(it) * B_TJ; };
+  // the block's query box: its query tiles are candidate tiles too
+  if (w == 0) {
+    float2 b = make_float2(INFINITY, -INFINITY);
+    float nq = 0.0f;
+    const float2* box2 = reinterpret_cast<const float2*>(box4);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int qt = qblock / B_TJ + u;
+      if (qt < ntiles) {
+        if (lane < BOX_D) {
+          const float2 v = box2[qt * BOX_D + lane];
+          b.x = fminf(b.x, v.x);
+          b.y = fmaxf(b.y, v.y);
+        }
+        nq = fmaxf(nq, tnrm[qt]);
+      }
+    }
+    if (lane < BOX_D) reinterpret_cast<float2*>(qbox)[lane] = b;
+    if (lane == 0) qnrm_s = nq;
+    if (lane < 4) tmax_s[1][lane] = FLT_MAX;
+  }
+  __syncthreads();
+  // live positions of the window [p0, p0 + 64) under threshold bound tm
+  auto window = [&](int p0, float tm) -> uint64_t {
+    const int p = p0 + lane;
+    bool live = p < ntiles;
+    if (tm < FLT_MAX) {
+      const float4* tb = box4 + tile_of(live ? p : 0) * (BOX_D / 2);
+      float lb = 0.0f;
+#pragma unroll 2
+      for (int h = 0; h < BOX_D / 2; ++h) {
+        const float4 v = tb[h], q = qbox[h];  // (lo, hi) of coordinates 2h and 2h + 1
+        const float g0 = fmaxf(fmaxf(v.x - q.y, q.x - v.y), 0.0f);
+        const float g1 = fmaxf(fmaxf(v.z - q.w, q.z - v.w), 0.0f);
+        lb = fmaf(g0, g0, lb);
+        lb = fmaf(g1, g1, lb);
+      }
+      const float margin = (qnrm_s + tnrm[tile_of(live ? p : 0)]) * (1.0f / 4096.0f);
+      live = live && !(lb > tm + margin);
+    }
+    return __ballot(live);
+  };
+  int wb = 0;  // first position of the current window
+  uint64_t win = window(0, FLT_MAX);
+  int pos = 0, buf = 0, par = 0;
   load_tile(tile_c0(0), 0);
-  int buf = 0;
-  for (int it = 0; it < ntiles; ++it) {
-    const int c0 = tile_c0(it);
+  while (pos < ntiles) {
+    const int c0 = tile_c0(pos);
     __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the tile has landed
     __syncthreads();                // ... and every wave's; the other buffer is free
+    // the next live position, under the thresholds of the previous tile
+    const float tm = __builtin_amdgcn_readfirstlane(__float_as_int(fmaxf(fmaxf(tmax_s[par ^ 1][0], tmax_s[par ^ 1][1]),
+                                                                        fmaxf(tmax_s[par ^ 1][2], tmax_s[par ^ 1][3]))));
+    int nxt = pos + 1;
+    while (nxt < ntiles) {
+      if (nxt >= wb + 64) {
+        wb = nxt;
+        win = window(wb, __int_as_float(tm));
+      }
+      const uint64_t m = win >> (nxt - wb);
+      if (m) {
+        nxt += __builtin_ctzll(m);
+        break;
+      }
+      nxt = wb + 64;
+    }
     // fetch the next tile while this one is consumed
-    if (it + 1 < ntiles) load_tile(tile_c0(it + 1), buf ^ 1);
+    if (nxt < ntiles) load_tile(tile_c0(nxt), buf ^ 1);
     const uint4* tl = tile[buf];
     const int32_t* pt = ptile[buf];
     // tiles that hold some of this block's queries exclude the self pairs;
@@ -648,7 +894,16 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
           tau_key[tt] = key_of(nt);
         }
     }
+    // this wave's largest threshold (padding queries hold -inf), read by
+    // every wave after the next barrier
+    {
+      const float m4 = fmaxf(fmaxf(tau[0], tau[1]), fmaxf(tau[2], tau[3]));
+      const float wm = -wave_min(-m4);
+      if (lane == 0) tmax_s[par][w] = wm;
+    }
+    par ^= 1;
     buf ^= 1;
+    pos = nxt;
   }
   for (int r = 0; r < 64; ++r) {
     const int qi = qbase + r;
@@ -736,27 +991,31 @@ __global__ __launch_bounds__(256) void count_nonfinite_kernel(const float* __res
 
 struct KnnLayout {
   int epl;
-  size_t o_buf, o_xq, o_xc, o_cand, o_perm, o_key, o_rng, o_hist, o_cur, o_off, o_bsum, bytes;
-  static KnnLayout make(int64_t n, int k, int precision, int ncand) {
+  size_t o_buf, o_xq, o_xc, o_xs, o_cand, o_perm, o_key, o_rng, o_hist, o_cur, o_off, o_bsum, o_box, o_tnrm, bytes;
+  static KnnLayout make(int64_t n, int d, int precision, int ncand) {
     KnnLayout L;
     Carve c;
+    L.epl = 8;  // capacity 512: room for 384 (FP32) or 448 (BF16) appends between compactions
+    L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * size_t(64 * L.epl));
+    // the locality order (both paths)
+    L.o_perm = c.take(sizeof(int32_t) * size_t(bf16_rows(n)));  // padded like the BF16 candidate rows
+    L.o_key = c.take(sizeof(uint16_t) * size_t(n));
+    L.o_rng = c.take(sizeof(uint32_t) * 2 * LOC_DIMS);
+    L.o_hist = c.take(sizeof(int) * LOC_BINS);
+    L.o_cur = c.take(sizeof(int) * LOC_BINS);
+    L.o_off = c.take(sizeof(int64_t) * (LOC_BINS + 1));
+    L.o_bsum = c.take(sizeof(int64_t) * (size_t(ceil_div(LOC_BINS + 1, SCAN_CHUNK)) + 1));
     if (precision == TSNE_KNN_FP32) {
-      L.epl = 8;  // capacity 512: room for 384 appends between compactions
-      L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * size_t(64 * L.epl));
-      L.o_xq = L.o_xc = L.o_cand = L.o_perm = L.o_key = L.o_rng = L.o_hist = L.o_cur = L.o_off = L.o_bsum = 0;
+      L.o_xs = c.take(sizeof(float) * size_t(n) * size_t(d));  // X in the locality order
+      L.o_xq = L.o_xc = L.o_cand = L.o_tnrm = 0;
+      L.o_box = c.take(sizeof(float2) * BOX_D * size_t(ceil_div(n, F_COLS)));
     } else {
-      L.epl = 8;  // capacity 512, headroom 64 per tile
-      L.o_buf = c.take(sizeof(uint64_t) * size_t(n) * 512);
+      L.o_xs = 0;
       L.o_xq = c.take(sizeof(uint16_t) * size_t(n) * 64);
       L.o_xc = c.take(sizeof(uint16_t) * size_t(bf16_rows(n)) * 64);  // + the infinite rows
       L.o_cand = c.take(sizeof(int32_t) * size_t(n) * size_t(ncand));
-      L.o_perm = c.take(sizeof(int32_t) * size_t(bf16_rows(n)));  // padded like the candidate rows
-      L.o_key = c.take(sizeof(uint16_t) * size_t(n));
-      L.o_rng = c.take(sizeof(uint32_t) * 2 * LOC_DIMS);
-      L.o_hist = c.take(sizeof(int) * LOC_BINS);
-      L.o_cur = c.take(sizeof(int) * LOC_BINS);
-      L.o_off = c.take(sizeof(int64_t) * (LOC_BINS + 1));
-      L.o_bsum = c.take(sizeof(int64_t) * (size_t(ceil_div(LOC_BINS + 1, SCAN_CHUNK)) + 1));
+      L.o_box = c.take(sizeof(float2) * BOX_D * size_t(ceil_div(n, B_TJ)));
+      L.o_tnrm = c.take(sizeof(float) * size_t(ceil_div(n, B_TJ)));
     }
     L.bytes = c.off;
     return L;
@@ -775,7 +1034,7 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   if (k > TSNE_MAX_K || d > TSNE_MAX_D) return TSNE_ERR_UNSUPPORTED;
   if (precision == TSNE_KNN_BF16 && (n_cand > TSNE_MAX_K || d > TSNE_MAX_D_BF16)) return TSNE_ERR_UNSUPPORTED;
   if (n > (int64_t(1) << 31) - 1) return TSNE_ERR_UNSUPPORTED;
-  const KnnLayout L = KnnLayout::make(n, k, precision, n_cand);
+  const KnnLayout L = KnnLayout::make(n, d, precision, n_cand);
   int rc = workspace_protocol(workspace, workspace_bytes, L.bytes);
   if (rc >= 0) return rc;
   TSNE_REQUIRE_GFX950();
@@ -790,20 +1049,8 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
     hipLaunchKernelGGL(count_nonfinite_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, X, cnt, nf);
     TSNE_CHECK_LAUNCH();
   }
-  if (precision == TSNE_KNN_FP32) {
-    if (fknn_small_blocks(n))
-      hipLaunchKernelGGL((knn_fp32_kernel<8, 8>), dim3(unsigned(ceil_div(n, 32))), dim3(256), 0, s, X, n, d, k, bufs,
-                         nbr_idx, nbr_d2);
-    else
-      hipLaunchKernelGGL((knn_fp32_kernel<8, 16>), dim3(unsigned(ceil_div(n, 64))), dim3(256), 0, s, X, n, d, k, bufs,
-                         nbr_idx, nbr_d2);
-    TSNE_CHECK_LAUNCH();
-    return TSNE_OK;
-  }
-  uint16_t* Xq = reinterpret_cast<uint16_t*>(ws + L.o_xq);
-  uint16_t* Xc = reinterpret_cast<uint16_t*>(ws + L.o_xc);
-  int32_t* cand = reinterpret_cast<int32_t*>(ws + L.o_cand);
-  // locality order: key range, keys and their counts, offsets, scatter
+  // locality order (both paths): key range, keys and their counts,
+  // offsets, scatter
   uint32_t* rng = reinterpret_cast<uint32_t*>(ws + L.o_rng);
   uint16_t* key = reinterpret_cast<uint16_t*>(ws + L.o_key);
   int* hist = reinterpret_cast<int*>(ws + L.o_hist);
@@ -824,15 +1071,41 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
   if ((rc = exclusive_scan<int>(hist, LOC_BINS, off, bsum, s))) return rc;
   hipLaunchKernelGGL(loc_scatter_kernel, lgrid, dim3(256), 0, s, key, n, off, cur, perm);
   TSNE_CHECK_LAUNCH();
+  if (precision == TSNE_KNN_FP32) {
+    float* Xs = reinterpret_cast<float*>(ws + L.o_xs);
+    float2* box = reinterpret_cast<float2*>(ws + L.o_box);
+    const int64_t ntc = ceil_div(n, F_COLS);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, perm, Xs);
+    TSNE_CHECK_LAUNCH();
+    hipLaunchKernelGGL(f32_box_kernel, dim3(unsigned(ceil_div(ntc, 4))), dim3(256), 0, s, Xs, n, d, ntc, box);
+    TSNE_CHECK_LAUNCH();
+    const float4* box4 = reinterpret_cast<const float4*>(box);
+    if (fknn_small_blocks(n))
+      hipLaunchKernelGGL((knn_fp32_kernel<8, 8>), dim3(unsigned(ceil_div(n, 32))), dim3(256), 0, s, Xs, perm, box4, n,
+                         d, k, bufs, nbr_idx, nbr_d2);
+    else
+      hipLaunchKernelGGL((knn_fp32_kernel<8, 16>), dim3(unsigned(ceil_div(n, 64))), dim3(256), 0, s, Xs, perm, box4,
+                         n, d, k, bufs, nbr_idx, nbr_d2);
+    TSNE_CHECK_LAUNCH();
+    return TSNE_OK;
+  }
+  uint16_t* Xq = reinterpret_cast<uint16_t*>(ws + L.o_xq);
+  uint16_t* Xc = reinterpret_cast<uint16_t*>(ws + L.o_xc);
+  int32_t* cand = reinterpret_cast<int32_t*>(ws + L.o_cand);
   // the padding of perm (the infinite candidate rows) names point 0; such a
   // candidate never passes a threshold, so the value is never used
   if ((rc = launch_fill<int32_t>(perm + n, bf16_rows(n) - n, 0, s))) return rc;
   hipLaunchKernelGGL(bf16_prep_kernel, dim3(unsigned(ceil_div(bf16_rows(n), 4))), dim3(256), 0, s, X, n, bf16_rows(n),
                      d, perm, Xq, Xc);
   TSNE_CHECK_LAUNCH();
+  const int64_t ntiles = ceil_div(n, B_TJ);
+  float2* box = reinterpret_cast<float2*>(ws + L.o_box);
+  float* tnrm = reinterpret_cast<float*>(ws + L.o_tnrm);
+  hipLaunchKernelGGL(bf16_box_kernel, dim3(unsigned(ceil_div(ntiles, 4))), dim3(256), 0, s, Xq, n, d, ntiles, box, tnrm);
+  TSNE_CHECK_LAUNCH();
   hipLaunchKernelGGL(knn_bf16_kernel<8>, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
-                     reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), perm, n, n_cand, bufs,
-                     cand);
+                     reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), perm,
+                     reinterpret_cast<const float4*>(box), tnrm, n, n_cand, bufs, cand);
   TSNE_CHECK_LAUNCH();
   if (d % 2 == 0 && reinterpret_cast<uintptr_t>(X) % 8 == 0)
     hipLaunchKernelGGL((rerank_kernel<TSNE_MAX_D_BF16, true>), dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n,

@@ -133,3 +133,55 @@ def test_knn_bf16_c3_sampled_rows(dev):
     oi, od = oracle.knn(X, 90, rows=rows)
     raw, adj = check_knn(X, rows, gi[rows], gd[rows], oi, od, min_agree=0.999)
     say("bf16 c3 agreement", raw, adj)
+
+
+def separated_clusters(n, d, clusters, seed):
+    """Far-apart Gaussian clusters (centres N(0, 30^2 I), unit noise): most
+    candidate tiles of a query block lie in other clusters, far beyond its
+    thresholds, so the BF16 sweep skips them."""
+    rng = np.random.default_rng(seed)
+    centres = rng.standard_normal((clusters, d)) * 30.0
+    lab = rng.integers(0, clusters, n)
+    return (centres[lab] + rng.standard_normal((n, d))).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,d,clusters", [(20001, 40, 16), (12345, 7, 10)])
+def test_knn_bf16_tile_skipping(dev, n, d, clusters):
+    # Candidate tiles whose box bound exceeds every threshold of a query
+    # block are not evaluated; the result must still be the exact kNN (all
+    # rows against the oracle) and, with n_cand = k, the candidate set the
+    # kNN of the bf16-rounded points.  d = 7 leaves box coordinates past d.
+    say("knn bf16 tile skipping", n, d, clusters)
+    X = separated_clusters(n, d, clusters, n + d)
+    k = 30
+    oi, od = oracle.knn(X, k)
+    gi, gd = gpu_knn(dev, X, k, "bf16", n_cand=2 * k)
+    raw, adj = check_knn(X, np.arange(n), gi, gd, oi, od, min_agree=0.999)
+    say("bf16 agreement with skipping", raw, adj)
+    ri, _ = oracle.knn(X, k, bf16_points=True)
+    ci, _ = gpu_knn(dev, X, k, "bf16", n_cand=k)
+    hits = np.mean([len(set(a) & set(b)) / k for a, b in zip(ci.tolist(), ri.tolist())])
+    assert hits >= 0.999, hits
+
+
+def test_knn_bf16_tile_skipping_nonfinite_rows(dev):
+    # Rows with a NaN or an infinite coordinate in several tiles: the boxes
+    # leave NaN out and stretch to infinity, and the finite rows still get
+    # their exact neighbours among the finite points.
+    say("knn bf16 tile skipping with non-finite rows")
+    n, d, k = 16000, 24, 20
+    X = separated_clusters(n, d, 12, 99)
+    rng = np.random.default_rng(100)
+    bad = rng.choice(n, 40, replace=False)
+    for t, r in enumerate(bad):
+        X[r, rng.integers(0, d)] = [np.nan, np.inf, -np.inf][t % 3]
+    fin = np.setdiff1d(np.arange(n), bad)
+    Xf = X[fin]
+    gi, gd = gpu_knn(dev, X, k, "bf16", n_cand=2 * k)
+    rows = rng.choice(fin.size, 2000, replace=False)
+    oi, od = oracle.knn(Xf, k, rows=rows)
+    g = gi[fin[rows]]
+    assert np.isin(g, fin).all()  # no non-finite point is a neighbour of a finite row
+    back = np.searchsorted(fin, g)
+    raw, adj = check_knn(Xf, rows, back.astype(np.int32), gd[fin[rows]], oi, od, min_agree=0.999)
+    say("bf16 agreement, finite rows", raw, adj)
