@@ -50,9 +50,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
-# the all-pairs kernel's arithmetic floor without packed FP32: 17 flops per
-# unordered pair over 12 issue cycles of a 64-lane wave, 1024 SIMDs, 2.4 GHz
-ISSUE_FLOOR_TFLOPS = 17.0 * 64 / (12 * 4) * 1024 * 2.4e9 / 1e12
+# the all-pairs kernel's instruction-issue ceiling without packed FP32: 17
+# flops per unordered pair over its 10 non-transcendental VALU instructions,
+# each one 4-cycle issue slot of a 64-lane wave, the reciprocal running on
+# the transcendental unit beside them; 1024 SIMDs, 2.4 GHz
+ISSUE_FLOOR_TFLOPS = 17.0 * 64 / (10 * 4) * 1024 * 2.4e9 / 1e12
 BF16_PEAK_TFLOPS = 2500.0  # dense
 HBM_PEAK_GBS = 8000.0
 
@@ -684,9 +686,9 @@ def main():
                 "flops_per_call": flops_per_call, "ms_per_call": grad_ms_mean,
                 "flops_per_ordered_pair": api.KLGRAD_FLOPS_PER_ORDERED_PAIR, "source_digest": digest,
                 "issue_floor": {"tflops": ISSUE_FLOOR_TFLOPS, "frac": achieved_tflops / ISSUE_FLOOR_TFLOPS,
-                                "basis": "12 VALU issue cycles of a wave per unordered pair (11 instructions, the "
-                                         "reciprocal taking two cycles) at 2.4 GHz on 1024 SIMDs, 17 flops per "
-                                         "pair; packed FP32 is not used"}}
+                                "basis": "10 non-transcendental VALU instructions per unordered pair, one 4-cycle "
+                                         "issue slot of a wave each, the reciprocal on the transcendental unit beside "
+                                         "them, at 2.4 GHz on 1024 SIMDs, 17 flops per pair; packed FP32 is not used"}}
     rec = {
         "metric": "KL-grad pair interactions/s + kNN build s, BF16-MFMA vs FP32 at stated error",
         "value": value,

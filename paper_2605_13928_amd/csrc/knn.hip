@@ -652,22 +652,24 @@ __device__ __forceinline__ int tile_slot(int r, int c) { return r * 8 + (c ^ (r 
 // selection is bound by memory instructions, so resident waves count more
 // than registers), and 1024 resident blocks cover 262144 queries in one
 // round.
-// Tile skipping.  A tile is neither fetched nor evaluated when no distance
-// in it can pass the threshold of any of the block's queries: with B the
-// box of the block's queries and T the tile's (leading BOX_D coordinates),
-// LB = sum_c gap_c(B, T)^2 is at most the squared distance of any query to
+// Tile skipping.  A wave does not evaluate a tile in which no distance can
+// pass the threshold of any of its 64 queries, and the block does not
+// fetch a tile that none of its waves evaluates.  With B the box of the
+// wave's queries (they are one tile of the order, so B is that tile's box)
+// and T the candidate tile's (leading BOX_D coordinates), LB = sum_c
+// gap_c(B, T)^2 is at most the squared distance of any of the queries to
 // any candidate of the tile, and the MFMA's distance differs from the
 // exact one of the rounded points by less than 2^-15 (N_q + N_c) (64
 // products of exact bf16 pairs, FP32 accumulation; N the squared norms, a
 // sum of absolute terms of at most 2 (N_q + N_c); the norm's bf16 parts
 // add 2^-20 of it), so LB > tau_max + 2^-12 (N_q + N_c), with tau_max the
-// block's largest threshold, means every distance of the tile exceeds
-// every query's threshold: the tile would append nothing, and skipping it
-// changes no buffer.  The outputs are those of the full sweep, bit for bit.
-// The test is taken for windows of 64 sweep positions at a time (one
-// position per lane), with the thresholds the waves published at the end
-// of the previous tile; they only decrease, so a stale value skips less,
-// never wrongly.
+// wave's largest threshold, means every distance of the tile exceeds every
+// threshold of the wave: the tile would append nothing for it, and
+// skipping it changes no buffer.  The outputs are those of the full sweep,
+// bit for bit.  The test is taken for windows of 64 sweep positions at a
+// time (one position per lane, a ballot per wave, the four masks OR-ed
+// through LDS), with the thresholds of that moment; they only decrease, so
+// a window's stale value skips less, never wrongly.
 template <int EPL>
 __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restrict__ Xq, const uint4* __restrict__ Xc,
                                                        const int32_t* __restrict__ perm, const float4* __restrict__ box4,
@@ -677,9 +679,9 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
   __shared__ uint4 tile[2][B_TJ * 8];  // double-buffered: 64 rows x 128 bytes each
   __shared__ int32_t ptile[2][B_TJ];    // the original indices of those rows
   __shared__ uint32_t hist_s[4][256];   // per-wave radix-select histograms
-  __shared__ float4 qbox[BOX_D / 2];    // box of the block's queries: (lo, hi) of two coordinates each
-  __shared__ float qnrm_s;              // bound on the squared norms of the block's queries
-  __shared__ float tmax_s[2][4];        // each wave's largest threshold, by tile parity
+  __shared__ float4 qbox[4][BOX_D / 2];  // box of each wave's queries: (lo, hi) of two coordinates each
+  __shared__ float qnrm_s[4];            // bound on the squared norms of each wave's queries
+  __shared__ uint64_t wmask_s[2][4];     // each wave's live positions, by window parity
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q16 = lane & 15, g4 = lane >> 4;
   // indices are 32-bit (n < 2^31 is checked by the caller); products that
@@ -745,68 +747,69 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
     return ti < ntiles ? ti : ti - ntiles;
   };
   auto tile_c0 = [&](int it) -> int { return tile_of(it) * B_TJ; };
-  // the block's query box: its query tiles are candidate tiles too
-  if (w == 0) {
-    float2 b = make_float2(INFINITY, -INFINITY);
-    float nq = 0.0f;
-    const float2* box2 = reinterpret_cast<const float2*>(box4);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int qt = qblock / B_TJ + u;
-      if (qt < ntiles) {
-        if (lane < BOX_D) {
-          const float2 v = box2[qt * BOX_D + lane];
-          b.x = fminf(b.x, v.x);
-          b.y = fmaxf(b.y, v.y);
-        }
-        nq = fmaxf(nq, tnrm[qt]);
-      }
-    }
-    if (lane < BOX_D) reinterpret_cast<float2*>(qbox)[lane] = b;
-    if (lane == 0) qnrm_s = nq;
-    if (lane < 4) tmax_s[1][lane] = FLT_MAX;
+  // each wave's query box: its 64 queries are candidate tile qblock / 64 + w
+  const int qt = qblock / B_TJ + w;
+  const bool has_q = qt < ntiles;  // else the wave holds only padding queries
+  if (has_q) {
+    if (lane < BOX_D / 2) qbox[w][lane] = box4[qt * (BOX_D / 2) + lane];
+    if (lane == 0) qnrm_s[w] = tnrm[qt];
   }
   __syncthreads();
-  // live positions of the window [p0, p0 + 64) under threshold bound tm
-  auto window = [&](int p0, float tm) -> uint64_t {
+  // live positions of the window [p0, p0 + 64): this wave's (returned) and
+  // the block's (any wave's, in `blk`); called by all waves together
+  int wpar = 0;
+  auto window = [&](int p0, uint64_t& blk) -> uint64_t {
+    // this wave's largest threshold now (padding queries hold -inf)
+    const float m4 = fmaxf(fmaxf(tau[0], tau[1]), fmaxf(tau[2], tau[3]));
+    const float tm = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(-wave_min(-m4))));
     const int p = p0 + lane;
-    bool live = p < ntiles;
+    bool live = has_q && p < ntiles;
     if (tm < FLT_MAX) {
-      const float4* tb = box4 + tile_of(live ? p : 0) * (BOX_D / 2);
+      const int t = tile_of(live ? p : 0);
+      const float4* tb = box4 + t * (BOX_D / 2);
       float lb = 0.0f;
 #pragma unroll 2
       for (int h = 0; h < BOX_D / 2; ++h) {
-        const float4 v = tb[h], q = qbox[h];  // (lo, hi) of coordinates 2h and 2h + 1
+        const float4 v = tb[h], q = qbox[w][h];  // (lo, hi) of coordinates 2h and 2h + 1
         const float g0 = fmaxf(fmaxf(v.x - q.y, q.x - v.y), 0.0f);
         const float g1 = fmaxf(fmaxf(v.z - q.w, q.z - v.w), 0.0f);
         lb = fmaf(g0, g0, lb);
         lb = fmaf(g1, g1, lb);
       }
-      const float margin = (qnrm_s + tnrm[tile_of(live ? p : 0)]) * (1.0f / 4096.0f);
+      const float margin = (qnrm_s[w] + tnrm[t]) * (1.0f / 4096.0f);
       live = live && !(lb > tm + margin);
     }
-    return __ballot(live);
+    const uint64_t mine = __ballot(live);
+    // two buffers: a wave may write the next window's mask while another
+    // still reads this one's
+    if (lane == 0) wmask_s[wpar][w] = mine;
+    __syncthreads();
+    blk = wmask_s[wpar][0] | wmask_s[wpar][1] | wmask_s[wpar][2] | wmask_s[wpar][3];
+    wpar ^= 1;
+    return mine;
   };
   int wb = 0;  // first position of the current window
-  uint64_t win = window(0, FLT_MAX);
-  int pos = 0, buf = 0, par = 0;
+  uint64_t win = 0;
+  uint64_t mine = window(0, win);
+  int pos = 0, buf = 0;
+  bool cur_mine = mine & 1;  // position 0 is live for every wave with queries
   load_tile(tile_c0(0), 0);
   while (pos < ntiles) {
     const int c0 = tile_c0(pos);
     __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the tile has landed
     __syncthreads();                // ... and every wave's; the other buffer is free
-    // the next live position, under the thresholds of the previous tile
-    const float tm = __builtin_amdgcn_readfirstlane(__float_as_int(fmaxf(fmaxf(tmax_s[par ^ 1][0], tmax_s[par ^ 1][1]),
-                                                                        fmaxf(tmax_s[par ^ 1][2], tmax_s[par ^ 1][3]))));
+    // the next position some wave evaluates
     int nxt = pos + 1;
+    bool nxt_mine = false;
     while (nxt < ntiles) {
       if (nxt >= wb + 64) {
         wb = nxt;
-        win = window(wb, __int_as_float(tm));
+        mine = window(wb, win);
       }
       const uint64_t m = win >> (nxt - wb);
       if (m) {
         nxt += __builtin_ctzll(m);
+        nxt_mine = (mine >> (nxt - wb)) & 1;
         break;
       }
       nxt = wb + 64;
@@ -872,8 +875,10 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
         }
       }
     };
-    if (c0 < qblock + 256 && qblock < c0 + B_TJ) sweep(std::true_type{});
-    else sweep(std::false_type{});
+    if (cur_mine) {
+      if (c0 < qblock + 256 && qblock < c0 + B_TJ) sweep(std::true_type{});
+      else sweep(std::false_type{});
+    }
     // compaction of queries that could overflow in the next tile; lanes
     // 0..15 speak for queries 16 t + lane
     uint64_t need = 0;
@@ -894,16 +899,9 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
           tau_key[tt] = key_of(nt);
         }
     }
-    // this wave's largest threshold (padding queries hold -inf), read by
-    // every wave after the next barrier
-    {
-      const float m4 = fmaxf(fmaxf(tau[0], tau[1]), fmaxf(tau[2], tau[3]));
-      const float wm = -wave_min(-m4);
-      if (lane == 0) tmax_s[par][w] = wm;
-    }
-    par ^= 1;
     buf ^= 1;
     pos = nxt;
+    cur_mine = nxt_mine;
   }
   for (int r = 0; r < 64; ++r) {
     const int qi = qbase + r;

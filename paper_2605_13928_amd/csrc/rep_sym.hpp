@@ -204,7 +204,11 @@ __device__ __forceinline__ int64_t sym_sched(int64_t pos, int64_t ns, bool last_
 // go to the i side, self pairs masked, Z weight 1 (else 2, via the caller).
 // CLEARJ: start the j-side sums at zero (else add to them).  ROWFENCE:
 // keep each row's 8 pairs together in the schedule (bounds the registers
-// that hold differences in flight).
+// that hold differences in flight) and spread the row's reciprocals
+// evenly over it, one per ten other VALU instructions: left to itself the
+// scheduler issues some reciprocals two to four instructions apart, where
+// they wait on one another in the transcendental unit (12-16 % of the
+// launch time).  Every caller sets it.
 template <bool DIAG, bool ZROW, bool CLEARJ = true, bool ROWFENCE = false>
 __device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)[8], const float4 (&pjv)[4],
                                          float (&rix)[8], float (&riy)[8], float (&zi)[8], float (&rj)[16],
@@ -245,7 +249,19 @@ __device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)
         if (ZROW) zj[c] += w;
       }
     }
-    if (ROWFENCE) __builtin_amdgcn_sched_barrier(0);
+    if (ROWFENCE) {
+      // the row's 8 reciprocals spread evenly over its 88 instructions:
+      // back-to-back reciprocals contend for the quarter-rate unit.  The
+      // first four VALU form the first pair's argument; after each
+      // reciprocal, ten VALU: the next pair's argument and this pair's uses
+      __builtin_amdgcn_sched_group_barrier(0x0002, 4, 0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        __builtin_amdgcn_sched_group_barrier(0x0400, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x0002, 10, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
@@ -266,9 +282,10 @@ struct AttList {
 // Fixed-point scale of the attraction sums (see the ATT phase below).
 constexpr float ATT_SCALE = 0x1p56f;
 
-// (256, 2): two workgroups per CU, i.e. at most 256 registers per lane, so
-// that two waves share each SIMD; the compiler otherwise lets the largest
-// instantiation grow past 256 and one wave per SIMD runs it 15 % slower.
+// (256, 2): two workgroups per CU (the LDS allows no more), at most 256
+// registers per lane, so that two waves share each SIMD; without the bound
+// the compiler lets the largest instantiation grow past 256, and one wave
+// per SIMD runs it 15 % slower.
 template <bool ZROW, int PF, bool ATT>
 __global__ __launch_bounds__(256, 2) void rep_sym_kernel(const float2* __restrict__ Y, int64_t n, int64_t ns,
                                                       float* __restrict__ part, float* __restrict__ zpart,
@@ -571,13 +588,13 @@ __global__ __launch_bounds__(256, 2) void rep_sym_kernel(const float2* __restric
         float rj[16], zj[8];
         float z = 0.0f;
         if (diag_sb && v == us) {
-          sym_tile<true, ZROW>(xi, yi, jc, rix, riy, zi, rj, zj, z, a == b);
+          sym_tile<true, ZROW, true, true>(xi, yi, jc, rix, riy, zi, rj, zj, z, a == b);
           zsum += double(z);
         } else {
           // this tile's slot of the wave's j accumulator, read early
           float2* dst = reinterpret_cast<float2*>(myj + comp * S + 64 * v + 8 * b + c0);
           float2 cur = *dst;
-          sym_tile<false, ZROW>(xi, yi, jc, rix, riy, zi, rj, zj, z, false);
+          sym_tile<false, ZROW, true, true>(xi, yi, jc, rix, riy, zi, rj, zj, z, false);
           zsum += 2.0 * double(z);
           // j side: reduce over the 8 lanes of this j-group, add into LDS
           float o0, o1;
@@ -681,6 +698,14 @@ __device__ __forceinline__ void sym_tile_z(const float (&xi)[8], const float (&y
       if (DIAG && r == c) w = same_group ? 0.0f : w;
       z += w;
     }
+    // one reciprocal per five other VALU, as in sym_tile
+    __builtin_amdgcn_sched_group_barrier(0x0002, 4, 0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      __builtin_amdgcn_sched_group_barrier(0x0400, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x0002, 5, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
