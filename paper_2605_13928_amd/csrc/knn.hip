@@ -257,10 +257,13 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(const float* __restric
 // Skipping test of the FP32 path.  Its distance sums d non-negative terms
 // (a rounded difference, squared and added by one FMA each), so it is at
 // least (1 - (d + 2) u) >= 1 - 2^-15 of the exact one for d <= 256; the
-// box bound LB (16 terms) is within 2^-19 of exact.  LB (1 - 2^-12) >
-// tau_max therefore means every distance of the tile exceeds every
-// threshold of the block: it would append nothing, and skipping it leaves
-// the buffers, and the outputs, as the full sweep makes them.
+// box bound LB (16 terms) is within 2^-19 of exact.  With the box of a
+// wave's 16 rows, LB (1 - 2^-12) > tau_max (the wave's largest threshold)
+// therefore means every distance of the tile exceeds every threshold of
+// the wave: it would append nothing for it, and skipping it leaves the
+// buffers, and the outputs, as the full sweep makes them.  The block
+// stages the tiles that some wave evaluates (the OR of the waves' window
+// masks, exchanged through LDS).
 template <int EPL, int F_RW>
 __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restrict__ Xs, const int32_t* __restrict__ perm,
                                                        const float4* __restrict__ cbox4, int64_t n, int d, int k,
@@ -274,8 +277,8 @@ __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restric
   __shared__ __attribute__((aligned(16))) float xj_s[F_DC * XJ_S];
   __shared__ uint32_t hist_s[4][256];  // per-wave radix-select histograms
   __shared__ int32_t pj_s[F_COLS];     // the points of the staged columns
-  __shared__ float4 qbox[BOX_D / 2];   // box of the block's rows: (lo, hi) of two coordinates each
-  __shared__ float tmax_s[2][4];       // each wave's largest threshold, by tile parity
+  __shared__ float4 qbox[4][BOX_D / 2];  // box of each wave's rows: (lo, hi) of two coordinates each
+  __shared__ uint64_t wmask_s[2][4];     // each wave's live positions, by window parity
   const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t row0 = int64_t(blockIdx.x) * F_ROWS;
   __shared__ int cnt_s[F_ROWS];  // buffer counts (appended by LDS atomics)
@@ -284,13 +287,15 @@ __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restric
   float tau[F_RW];
 #pragma unroll
   for (int r = 0; r < F_RW; ++r) tau[r] = row0 + w * F_RW + r < n ? INFINITY : -INFINITY;  // rows past n never accept
-  if (w == 0) {
-    // the block's box (rows past n left out)
+  const int64_t wrow0 = row0 + w * F_RW;  // this wave's rows
+  const bool has_rows = wrow0 < n;
+  {
+    // this wave's box (rows past n left out)
     const int c = lane & 15, g = lane >> 4;
     float lo = INFINITY, hi = -INFINITY;
     if (c < d) {
-      for (int r = g; r < F_ROWS && row0 + r < n; r += 4) {
-        const float v = Xs[(row0 + r) * d + c];
+      for (int r = g; r < F_RW && wrow0 + r < n; r += 4) {
+        const float v = Xs[(wrow0 + r) * d + c];
         lo = fminf(lo, v);
         hi = fmaxf(hi, v);
       }
@@ -299,8 +304,8 @@ __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restric
     lo = fminf(lo, xor_lane_f(lo, 32));
     hi = fmaxf(hi, xor_lane_f(hi, 16));
     hi = fmaxf(hi, xor_lane_f(hi, 32));
-    if (lane < BOX_D) reinterpret_cast<float2*>(qbox)[lane] = lane < d ? make_float2(lo, hi) : make_float2(0.0f, 0.0f);
-    if (lane < 4) tmax_s[1][lane] = INFINITY;
+    if (lane < BOX_D)
+      reinterpret_cast<float2*>(qbox[w])[lane] = lane < d ? make_float2(lo, hi) : make_float2(0.0f, 0.0f);
   }
   const bool one_chunk = d <= F_DC;
   if (one_chunk) stage_rows_t(xi_s, XI_S, Xs, row0, F_ROWS, n, d, 0, d);
@@ -311,16 +316,22 @@ __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restric
     const int ti = tstart + it;
     return ti < ntc ? ti : ti - ntc;
   };
-  // live positions of the window [p0, p0 + 64) under the threshold bound tm
-  auto window = [&](int p0, float tm) -> uint64_t {
+  // live positions of the window [p0, p0 + 64): this wave's (returned) and
+  // the block's (any wave's, in `blk`); called by all waves together
+  int wpar = 0;
+  auto window = [&](int p0, uint64_t& blk) -> uint64_t {
+    // this wave's largest threshold now (uniform per row; rows past n hold -inf)
+    float tm = tau[0];
+#pragma unroll
+    for (int r = 1; r < F_RW; ++r) tm = fmaxf(tm, tau[r]);
     const int p = p0 + lane;
-    bool live = p < ntc;
+    bool live = has_rows && p < ntc;
     if (tm < INFINITY) {
       const float4* tb = cbox4 + tile_of(live ? p : 0) * (BOX_D / 2);
       float lb = 0.0f;
 #pragma unroll 2
       for (int h = 0; h < BOX_D / 2; ++h) {
-        const float4 v = tb[h], q = qbox[h];  // (lo, hi) of coordinates 2h and 2h + 1
+        const float4 v = tb[h], q = qbox[w][h];  // (lo, hi) of coordinates 2h and 2h + 1
         const float g0 = fmaxf(fmaxf(v.x - q.y, q.x - v.y), 0.0f);
         const float g1 = fmaxf(fmaxf(v.z - q.w, q.z - v.w), 0.0f);
         lb = fmaf(g0, g0, lb);
@@ -328,24 +339,32 @@ __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restric
       }
       live = live && !(lb * (1.0f - 1.0f / 4096.0f) > tm);
     }
-    return __ballot(live);
+    const uint64_t mine = __ballot(live);
+    // two buffers: a wave may write the next window's mask while another
+    // still reads this one's
+    if (lane == 0) wmask_s[wpar][w] = mine;
+    __syncthreads();
+    blk = wmask_s[wpar][0] | wmask_s[wpar][1] | wmask_s[wpar][2] | wmask_s[wpar][3];
+    wpar ^= 1;
+    return mine;
   };
   int wb = -64;  // first position of the current window (none yet)
-  uint64_t win = 0;
-  int from = 0, par = 0;
+  uint64_t win = 0, mine = 0;
+  int from = 0;
   for (;;) {
-    __syncthreads();  // every wave is done with the previous tile; thresholds published
-    const float tm = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(
-        fmaxf(fmaxf(tmax_s[par ^ 1][0], tmax_s[par ^ 1][1]), fmaxf(tmax_s[par ^ 1][2], tmax_s[par ^ 1][3])))));
+    __syncthreads();  // every wave is done with the previous tile
+    // the next position some wave evaluates
     int pos = from;
+    bool pos_mine = false;
     while (pos < ntc) {
       if (pos >= wb + 64) {
         wb = pos;
-        win = window(wb, tm);
+        mine = window(wb, win);
       }
       const uint64_t m = win >> (pos - wb);
       if (m) {
         pos += __builtin_ctzll(m);
+        pos_mine = (mine >> (pos - wb)) & 1;
         break;
       }
       pos = wb + 64;
@@ -362,6 +381,7 @@ __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restric
       stage_rows_t(xj_s, XJ_S, Xs, c0, F_COLS, n, d, dc, dl);
       if (dc == 0 && tid < F_COLS) pj_s[tid] = c0 + tid < n ? perm[c0 + tid] : -1;
       __syncthreads();
+      if (!pos_mine) continue;  // no distance of this tile can pass a threshold of this wave
       for (int c = 0; c < dl; ++c) {
         const float4* ap = reinterpret_cast<const float4*>(&xi_s[c * XI_S + w * F_RW]);
         float a[F_RW];
@@ -388,7 +408,7 @@ __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restric
     bool any = false;
 #pragma unroll
     for (int r = 0; r < F_RW; ++r) any |= (acc[r][0] <= tau[r]) | (acc[r][1] <= tau[r]);
-    if (__ballot(any)) {
+    if (pos_mine && __ballot(any)) {
       const bool edge = (c0 + F_COLS > n) || (c0 < row0 + F_ROWS && row0 < c0 + F_COLS);
       const int64_t j0 = c0 + lane * 2;
       const int32_t pj0 = pj_s[lane * 2], pj1 = pj_s[lane * 2 + 1];
@@ -420,15 +440,6 @@ __global__ __launch_bounds__(256, 3) void knn_fp32_kernel(const float* __restric
           if (rr == r) tau[rr] = nt;
       }
     }
-    // this wave's largest threshold (uniform per row), read by every wave
-    // after the next barrier
-    if (lane == 0) {
-      float m = tau[0];
-#pragma unroll
-      for (int r = 1; r < F_RW; ++r) m = fmaxf(m, tau[r]);
-      tmax_s[par][w] = m;
-    }
-    par ^= 1;
     from = pos + 1;
   }
   for (int r = 0; r < F_RW; ++r) {
