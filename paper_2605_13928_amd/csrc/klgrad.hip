@@ -341,21 +341,26 @@ __device__ __forceinline__ int64_t job_of(int64_t s, int64_t t, int64_t ns) {
 // block's rows lie in one superblock s and an entry (i, j), j > i, belongs
 // to job (s, j / S).  The block histograms its entries over the opposite
 // superblock t in LDS, ATT_BINS superblocks per pass, and touches each job's
-// global counter once per pass: a few global atomics per block instead of
-// one per entry.  The order of the entries inside a job's range follows the
+// global counter once per pass: at most ns global atomics per block instead
+// of one per entry.  ROWS is 256 where that still gives 1024 blocks or
+// more (at 10^6 points the 3907 blocks make 4 M such atomics, where 16-row
+// blocks made 56 M and took five times as long), else 16, so that small
+// problems keep enough blocks.  The order of the entries inside a job's
+// range follows the
 // LDS atomics; the all-pairs kernel sums them in exact fixed point, so the
 // order does not reach any result.
-constexpr int ATT_ROWS = 16;
-constexpr int ATT_BINS = 512;
+constexpr int ATT_BINS = 1024;
+inline bool att_big_blocks(int64_t n) { return ceil_div(n, 256) >= 1024; }
 
-// row of entry e among the block's rows (rp[0..ATT_ROWS]); e is increasing
-// per thread, so the search resumes from the previous row
+// row of entry e among the block's rows (rp[0..ROWS]); e is increasing per
+// thread, so the search resumes from the previous row
+template <int ROWS>
 __device__ __forceinline__ int att_row(const int64_t* rp, int64_t e, int r) {
-  while (r < ATT_ROWS - 1 && rp[r + 1] <= e) ++r;
+  while (r < ROWS - 1 && rp[r + 1] <= e) ++r;
   return r;
 }
 
-template <bool SCATTER>
+template <bool SCATTER, int ROWS>
 __global__ __launch_bounds__(256) void att_bucket_kernel(int64_t n, int64_t S, int64_t ns,
                                                          const int64_t* __restrict__ row_ptr,
                                                          const int32_t* __restrict__ col,
@@ -364,23 +369,24 @@ __global__ __launch_bounds__(256) void att_bucket_kernel(int64_t n, int64_t S, i
                                                          uint32_t* __restrict__ ij, float* __restrict__ p, int64_t cap) {
   __shared__ int h[ATT_BINS];
   __shared__ int64_t base[SCATTER ? ATT_BINS : 1];
-  __shared__ int64_t rp[ATT_ROWS + 1];
+  __shared__ int64_t rp[ROWS + 1];
   const int tid = threadIdx.x;
-  const int64_t r0 = int64_t(blockIdx.x) * ATT_ROWS;
-  const int64_t s = r0 / S;
-  if (tid <= ATT_ROWS) rp[tid] = row_ptr[r0 + tid < n ? r0 + tid : n];
+  const int lgS = __builtin_ctzll(uint64_t(S));  // S is a power of two: shifts, not 64-bit divisions
+  const int64_t r0 = int64_t(blockIdx.x) * ROWS;
+  const int64_t s = r0 >> lgS;
+  for (int q = tid; q <= ROWS; q += 256) rp[q] = row_ptr[r0 + q < n ? r0 + q : n];
   __syncthreads();
-  const int64_t E0 = rp[0], E1 = rp[ATT_ROWS];
+  const int64_t E0 = rp[0], E1 = rp[ROWS];
   for (int64_t w0 = s; w0 < ns; w0 += ATT_BINS) {  // opposite superblocks t >= s
     const int64_t w1 = w0 + ATT_BINS < ns ? w0 + ATT_BINS : ns;
     for (int b = tid; b < ATT_BINS; b += 256) h[b] = 0;
     __syncthreads();
     int r = 0;
     for (int64_t e = E0 + tid; e < E1; e += 256) {
-      r = att_row(rp, e, r);
+      r = att_row<ROWS>(rp, e, r);
       const int64_t i = r0 + r;
       const int32_t j = col[e];
-      const int64_t t = j / S;
+      const int64_t t = j >> lgS;
       if (j > i && j < n && t >= w0 && t < w1) atomicAdd(&h[t - w0], 1);
     }
     __syncthreads();
@@ -399,10 +405,10 @@ __global__ __launch_bounds__(256) void att_bucket_kernel(int64_t n, int64_t S, i
       __syncthreads();
       r = 0;
       for (int64_t e = E0 + tid; e < E1; e += 256) {
-        r = att_row(rp, e, r);
+        r = att_row<ROWS>(rp, e, r);
         const int64_t i = r0 + r;
         const int32_t j = col[e];
-        const int64_t t = j / S;
+        const int64_t t = j >> lgS;
         if (j > i && j < n && t >= w0 && t < w1) {
           const int64_t pos = base[t - w0] + atomicAdd(&h[t - w0], 1);
           if (pos < cap) {  // cap < entries only if the caller's nnz is wrong
@@ -441,15 +447,18 @@ int att_build(const AttPlan& A, const SymGrid& g, char* ws, int64_t n, const int
   int rc;
   if ((rc = launch_fill<int>(cnt, g.njobs, 0, s))) return rc;
   if ((rc = launch_fill<int>(cur, g.njobs, 0, s))) return rc;
-  const dim3 grid(unsigned(ceil_div(n, ATT_ROWS))), block(256);
-  hipLaunchKernelGGL(att_bucket_kernel<false>, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, val, cnt,
+  const bool big = att_big_blocks(n);
+  const dim3 grid(unsigned(ceil_div(n, big ? 256 : 16))), block(256);
+  auto count = big ? att_bucket_kernel<false, 256> : att_bucket_kernel<false, 16>;
+  hipLaunchKernelGGL(count, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, val, cnt,
                      static_cast<const int64_t*>(nullptr), static_cast<int*>(nullptr),
                      static_cast<uint32_t*>(nullptr), static_cast<float*>(nullptr), int64_t(0));
   TSNE_CHECK_LAUNCH();
   if ((rc = exclusive_scan<int>(cnt, g.njobs, off, bsum, s))) return rc;
   const int64_t cap = int64_t((A.o_p - A.o_ij) / sizeof(uint32_t));
-  hipLaunchKernelGGL(att_bucket_kernel<true>, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, val,
-                     static_cast<int*>(nullptr), off, cur, ij, p, cap);
+  auto scatter = big ? att_bucket_kernel<true, 256> : att_bucket_kernel<true, 16>;
+  hipLaunchKernelGGL(scatter, grid, block, 0, s, n, g.S, g.ns, row_ptr, col, val, static_cast<int*>(nullptr), off,
+                     cur, ij, p, cap);
   TSNE_CHECK_LAUNCH();
   *out = AttList{off, ij, p, cap};
   return TSNE_OK;
