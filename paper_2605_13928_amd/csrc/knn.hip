@@ -167,9 +167,10 @@ __device__ void emit_row(const uint64_t* __restrict__ buf, int c, int keep, int3
 // ---------------------------------------------------------------------
 // Tile skipping (both paths).  The points are put in a locality order
 // (below), so that a tile of consecutive positions is narrow in the leading
-// coordinates; a tile whose box is farther from the box of a block's
-// queries than every threshold of the block can hold no candidate for it,
-// and the sweep skips it.  Boxes span the leading BOX_D coordinates.
+// coordinates; a tile whose box is farther from the box of a wave's
+// queries than every threshold of the wave can hold no candidate for it,
+// so the wave skips it, and the block fetches only the tiles some wave
+// needs.  Boxes span the leading BOX_D coordinates.
 constexpr int BOX_D = 16;
 
 // ---------------------------------------------------------------------
@@ -180,7 +181,7 @@ constexpr int BOX_D = 16;
 // columns are positions of the locality order (Xs = X in that order; perm
 // maps a position to its point, which keys and outputs name); a block
 // sweeps the column tiles cyclically from the one before its own rows and
-// skips those its box test rules out.
+// skips those the box tests of its waves rule out.
 
 constexpr int F_COLS = 128;
 constexpr int F_DC = 56;
