@@ -251,7 +251,7 @@ __device__ __forceinline__ void sym_tile(const float (&xi)[8], const float (&yi)
     }
     if (ROWFENCE) {
       // the row's 8 reciprocals spread evenly over its 88 instructions:
-      // back-to-back reciprocals contend for the quarter-rate unit.  The
+      // back-to-back reciprocals contend for the half-rate unit.  The
       // first four VALU form the first pair's argument; after each
       // reciprocal, ten VALU: the next pair's argument and this pair's uses
       __builtin_amdgcn_sched_group_barrier(0x0002, 4, 0);
