@@ -924,27 +924,40 @@ __global__ __launch_bounds__(256, 4) void knn_bf16_kernel(const uint4* __restric
   }
 }
 
+// Rows of X padded to dp = d rounded up to 4 (zeros past d), 16-byte
+// aligned, for the re-rank's gathers: one wave per row.
+__global__ __launch_bounds__(256) void pad_rows_kernel(const float* __restrict__ X, int64_t n, int d, int dp,
+                                                       float* __restrict__ Xp) {
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int c = lane_id();
+  if (i >= n || c >= dp) return;
+  Xp[i * dp + c] = c < d ? X[i * d + c] : 0.0f;
+}
+
 // Re-rank: one wave per row; FP32 direct differences (same arithmetic as the
 // FP32 path: squares accumulated in dimension order) of the row's
 // candidates, sorted by (d, j); best k written.  Rows are taken in the
 // locality order (wave w re-ranks row perm[w]), so the waves resident at one
 // time gather overlapping candidate rows from the caches.  The query row is
 // read with uniform (scalar) loads; each lane issues all loads of a
-// candidate row before the arithmetic (d <= DMAX), two coordinates per load
-// when the rows are 8-byte aligned (PAIRS: d even and X 8-byte aligned),
-// which halves the scattered requests the address units must serve.
-template <int DMAX, bool PAIRS>
-__global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X, int64_t n, int d,
+// candidate row before the arithmetic, four coordinates per load from the
+// padded rows Xp (dp <= DP floats each), which quarters the scattered
+// requests the address units must serve; coordinates past dp re-read the
+// row's last four (in bounds) and, like the zeros past d, add an exact 0.
+template <int DP>
+__global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ Xp, int64_t n, int d, int dp,
                                                      const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
                                                      int ncand, int k, int32_t* __restrict__ out_idx,
                                                      float* __restrict__ out_d2) {
+  static_assert(DP % 4 == 0, "whole float4 loads");
   const int lane = lane_id();
   const int64_t pos = int64_t(__builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6)));
   if (pos >= n) return;
   const int64_t row = int64_t(__builtin_amdgcn_readfirstlane(perm[pos]));
-  float xi[DMAX];
+  float xi[DP];
 #pragma unroll
-  for (int c = 0; c < DMAX; ++c) xi[c] = c < d ? X[row * d + c] : 0.0f;
+  for (int c = 0; c < DP; ++c) xi[c] = c < d ? Xp[row * dp + c] : 0.0f;
+  const int last = dp / 4 - 1;
   uint64_t v[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -952,26 +965,19 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ X
     v[t] = KEY_MAX;
     const int32_t j = e < ncand ? cand[row * ncand + e] : -1;
     if (j >= 0 && j < n) {  // a row short of candidates (non-finite input) holds -1
-      const float* xj = X + int64_t(j) * d;
-      float xv[DMAX];
-      // no branches on d: coordinates past d re-read the row's last ones
-      // (in bounds) and add an exact 0 to the sum
-      if (PAIRS) {
-        const float2* xj2 = reinterpret_cast<const float2*>(xj);
-        const int last = d / 2 - 1;
+      const float4* xj4 = reinterpret_cast<const float4*>(Xp + int64_t(j) * dp);
+      float xv[DP];
 #pragma unroll
-        for (int c = 0; c < DMAX; c += 2) {
-          const float2 q = xj2[c / 2 < last ? c / 2 : last];
-          xv[c] = q.x;
-          if (c + 1 < DMAX) xv[c + 1] = q.y;
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < DMAX; ++c) xv[c] = xj[c < d ? c : d - 1];
+      for (int c = 0; c < DP; c += 4) {
+        const float4 q = xj4[c / 4 < last ? c / 4 : last];
+        xv[c] = q.x;
+        xv[c + 1] = q.y;
+        xv[c + 2] = q.z;
+        xv[c + 3] = q.w;
       }
       float s2 = 0.0f;
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) {
+      for (int c = 0; c < DP; ++c) {
         const float u = c < d ? xi[c] - xv[c] : 0.0f;
         s2 = __builtin_fmaf(u, u, s2);
       }
@@ -1001,7 +1007,8 @@ __global__ __launch_bounds__(256) void count_nonfinite_kernel(const float* __res
 
 struct KnnLayout {
   int epl;
-  size_t o_buf, o_xq, o_xc, o_xs, o_cand, o_perm, o_key, o_rng, o_hist, o_cur, o_off, o_bsum, o_box, o_tnrm, bytes;
+  size_t o_buf, o_xq, o_xc, o_xs, o_xp, o_cand, o_perm, o_key, o_rng, o_hist, o_cur, o_off, o_bsum, o_box, o_tnrm,
+      bytes;
   static KnnLayout make(int64_t n, int d, int precision, int ncand) {
     KnnLayout L;
     Carve c;
@@ -1017,10 +1024,11 @@ struct KnnLayout {
     L.o_bsum = c.take(sizeof(int64_t) * (size_t(ceil_div(LOC_BINS + 1, SCAN_CHUNK)) + 1));
     if (precision == TSNE_KNN_FP32) {
       L.o_xs = c.take(sizeof(float) * size_t(n) * size_t(d));  // X in the locality order
-      L.o_xq = L.o_xc = L.o_cand = L.o_tnrm = 0;
+      L.o_xq = L.o_xc = L.o_cand = L.o_tnrm = L.o_xp = 0;
       L.o_box = c.take(sizeof(float2) * BOX_D * size_t(ceil_div(n, F_COLS)));
     } else {
       L.o_xs = 0;
+      L.o_xp = c.take(sizeof(float) * size_t(n) * size_t((d + 3) / 4 * 4));  // X padded, for the re-rank
       L.o_xq = c.take(sizeof(uint16_t) * size_t(n) * 64);
       L.o_xc = c.take(sizeof(uint16_t) * size_t(bf16_rows(n)) * 64);  // + the infinite rows
       L.o_cand = c.take(sizeof(int32_t) * size_t(n) * size_t(ncand));
@@ -1117,12 +1125,17 @@ extern "C" int tsne_knn(const float* X, int64_t n, int32_t d, int32_t k, int32_t
                      reinterpret_cast<const uint4*>(Xq), reinterpret_cast<const uint4*>(Xc), perm,
                      reinterpret_cast<const float4*>(box), tnrm, n, n_cand, bufs, cand);
   TSNE_CHECK_LAUNCH();
-  if (d % 2 == 0 && reinterpret_cast<uintptr_t>(X) % 8 == 0)
-    hipLaunchKernelGGL((rerank_kernel<TSNE_MAX_D_BF16, true>), dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n,
-                       d, perm, cand, n_cand, k, nbr_idx, nbr_d2);
+  const int dp = (d + 3) / 4 * 4;
+  float* Xp = reinterpret_cast<float*>(ws + L.o_xp);
+  hipLaunchKernelGGL(pad_rows_kernel, dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n, d, dp, Xp);
+  TSNE_CHECK_LAUNCH();
+  // the exact width for the common 50-coordinate input, else the largest
+  if (dp == 52)
+    hipLaunchKernelGGL((rerank_kernel<52>), dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, Xp, n, d, dp, perm, cand,
+                       n_cand, k, nbr_idx, nbr_d2);
   else
-    hipLaunchKernelGGL((rerank_kernel<TSNE_MAX_D_BF16, false>), dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s, X, n,
-                       d, perm, cand, n_cand, k, nbr_idx, nbr_d2);
+    hipLaunchKernelGGL((rerank_kernel<(TSNE_MAX_D_BF16 + 3) / 4 * 4>), dim3(unsigned(ceil_div(n, 4))), dim3(256), 0, s,
+                       Xp, n, d, dp, perm, cand, n_cand, k, nbr_idx, nbr_d2);
   TSNE_CHECK_LAUNCH();
   return TSNE_OK;
 }
